@@ -1,0 +1,8 @@
+"""CPU oracle for the ENUF hot path (test infrastructure only).
+
+``ewald``       plain FP64 Ewald sum over explicit k-vectors (C + OpenMP)
+``enuf_mirror`` the ENUF gridding steps in plain numpy FP64
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package; the HIP library never imports, links or calls it.
+"""

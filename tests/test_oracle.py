@@ -1,0 +1,245 @@
+"""Pins for the FP64 direct-Ewald oracle (CPU only).
+
+Each test checks the oracle against something other than itself: a closed
+form (Madelung constants, the Wigner self-energy of a charge in a cubic box,
+the small-separation expansion of a periodic dipole pair), an invariant of
+the exact Ewald sum (alpha independence, translation, permutation,
+replication, Newton's third law, the quadratic-form identity), or finite
+differences of its own energy.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ewald as ew
+from paper_2004_12484_amd import inputs
+
+MADELUNG_NACL = 1.747564594633      # NaCl rock salt, nearest-neighbour units
+MADELUNG_CSCL = 1.762674773070      # CsCl, nearest-neighbour units
+WIGNER_SC = -2.837297479480619      # Ewald self-energy constant, simple cubic
+
+
+def _small_system(n=24, box=(7.0, 8.0, 9.5), seed=11, min_dist=0.8):
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, float)
+    pts = []
+    while len(pts) < n:
+        c = rng.uniform(0, 1, 3) * box
+        ok = True
+        for p in pts:
+            d = c - p
+            d -= box * np.round(d / box)
+            if np.linalg.norm(d) < min_dist:
+                ok = False
+                break
+        if ok:
+            pts.append(c)
+    x = np.array(pts)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * rng.uniform(0.5, 1.5, n)
+    q -= q.mean()  # neutral
+    return x, q, box
+
+
+def test_madelung_nacl_perfect_lattice():
+    w = inputs.nacl(noise=0.0)
+    L = w.box[0]
+    a = 5.64
+    expect = -(w.N / 2) * MADELUNG_NACL / (a / 2)
+    for aL in (10.0, 12.0, 14.0):
+        r = ew.ewald(w.x, w.q, w.box, aL / L, L / 2, tol=1e-20)
+        assert abs(r["E"] - expect) / abs(expect) < 2e-12
+        assert np.abs(r["F"]).max() < 1e-10
+
+
+def test_madelung_cscl():
+    n = 3
+    a = 1.0
+    idx = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    x = np.concatenate([idx, idx + 0.5]) * a
+    q = np.concatenate([np.ones(len(idx)), -np.ones(len(idx))])
+    L = n * a
+    box = np.array([L, L, L])
+    d_nn = a * math.sqrt(3) / 2
+    expect = -(len(q) / 2) * MADELUNG_CSCL / d_nn
+    r = ew.ewald(x, q, box, 12.0 / L, L / 2, tol=1e-20)
+    assert abs(r["E"] - expect) / abs(expect) < 1e-11
+
+
+@pytest.mark.parametrize("aL", [5.0, 7.0, 9.0])
+def test_wigner_single_charge(aL):
+    # one charge with its neutralising background: E = xi q^2 / (2L)
+    L = 3.7
+    q = np.array([1.3])
+    x = np.array([[0.4, 1.1, 2.9]])
+    box = np.array([L, L, L])
+    r = ew.ewald(x, q, box, aL / L, L / 2, tol=1e-20)
+    expect = WIGNER_SC * q[0] ** 2 / (2 * L)
+    assert abs(r["E"] - expect) / abs(expect) < 1e-10
+    assert r["E_bg"] != 0.0
+
+
+def test_dipole_pair_expansion():
+    # +q and -q at separation d in a large cubic box (tin-foil boundary):
+    # E = -q^2/d - 2 pi q^2 d^2 / (3V) + O(d^4/L^5), and the force on +q
+    # points at -q with |F| = q^2/d^2 - 4 pi q^2 d / (3V).
+    L, d, qq = 60.0, 1.0, 1.0
+    box = np.array([L, L, L])
+    x = np.array([[10.0, 11.0, 12.0], [10.0 + d, 11.0, 12.0]])
+    q = np.array([qq, -qq])
+    r = ew.ewald(x, q, box, 7.0 / L, L / 2, tol=1e-20)
+    V = L ** 3
+    e_exp = -qq * qq / d - 2 * math.pi * qq * qq * d * d / (3 * V)
+    assert abs(r["E"] - e_exp) < 5e-8
+    f_exp = qq * qq / d ** 2 - 4 * math.pi * qq * qq * d / (3 * V)
+    assert abs(r["F"][0, 0] - f_exp) < 5e-8
+    assert abs(r["F"][0, 1]) < 1e-9 and abs(r["F"][0, 2]) < 1e-9
+
+
+def test_alpha_invariance_perturbed_nacl():
+    w = inputs.nacl()
+    L = w.box[0]
+    es = [ew.ewald(w.x, w.q, w.box, aL / L, L / 2, tol=1e-20)["E"] for aL in (10.0, 12.0, 14.0)]
+    for e in es[1:]:
+        assert abs(e - es[0]) / abs(es[0]) < 1e-10
+
+
+def test_alpha_invariance_forces_orthorhombic():
+    x, q, box = _small_system()
+    rc = 0.5 * box.min()
+    rs = [ew.ewald(x, q, box, a / rc, rc, tol=1e-20) for a in (6.0, 6.5, 7.0)]
+    for r in rs[1:]:
+        assert abs(r["E"] - rs[0]["E"]) < 1e-10 * abs(rs[0]["E"])
+        assert np.abs(r["F"] - rs[0]["F"]).max() < 1e-9 * np.abs(rs[0]["F"]).max()
+        assert np.abs(r["phi"] - rs[0]["phi"]).max() < 1e-9 * np.abs(rs[0]["phi"]).max()
+
+
+def test_forces_are_minus_energy_gradient():
+    x, q, box = _small_system()
+    rc = 0.5 * box.min()
+    alpha = 6.0 / rc  # erfc(6) ~ 2e-17: no discontinuity at the cutoff
+    r = ew.ewald(x, q, box, alpha, rc, tol=1e-20)
+    h = 1e-5
+    for i in (0, 5, 17):
+        for d in range(3):
+            xp = x.copy(); xp[i, d] += h
+            xm = x.copy(); xm[i, d] -= h
+            fd = -(ew.energy(xp, q, box, alpha, rc, tol=1e-20) - ew.energy(xm, q, box, alpha, rc, tol=1e-20)) / (2 * h)
+            assert abs(fd - r["F"][i, d]) < 1e-6 * max(1.0, abs(r["F"][i, d]))
+
+
+def test_potential_is_charge_derivative():
+    x, q, box = _small_system(seed=3)
+    rc = 0.5 * box.min()
+    alpha = 6.0 / rc
+    r = ew.ewald(x, q, box, alpha, rc, tol=1e-20)
+    h = 1e-5
+    for i in (1, 9):
+        qp = q.copy(); qp[i] += h
+        qm = q.copy(); qm[i] -= h
+        fd = (ew.energy(x, qp, box, alpha, rc, tol=1e-20) - ew.energy(x, qm, box, alpha, rc, tol=1e-20)) / (2 * h)
+        assert abs(fd - r["phi"][i]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_quadratic_form_identity_non_neutral():
+    # E is a quadratic form in q, so sum_i q_i dE/dq_i = 2E (with a net charge,
+    # which exercises the background term).
+    x, q, box = _small_system(seed=5)
+    q = q + 0.3
+    rc = 0.5 * box.min()
+    r = ew.ewald(x, q, box, 5.0 / rc, rc, tol=1e-20)
+    assert abs(np.dot(q, r["phi"]) - 2 * r["E"]) < 1e-11 * abs(r["E"]) * len(q)
+
+
+def test_newton_third_law():
+    x, q, box = _small_system(seed=7)
+    rc = 0.45 * box.min()
+    r = ew.ewald(x, q, box, 3.0 / rc, rc)
+    fmax = np.abs(r["F"]).max()
+    assert np.abs(r["F_R"].sum(0)).max() < 1e-12 * fmax * len(q)
+    assert np.abs(r["F_K"].sum(0)).max() < 1e-12 * fmax * len(q)
+
+
+def test_minimum_image_equals_explicit_images():
+    x, q, box = _small_system(seed=9, n=30)
+    for rc in (0.3 * box.min(), 0.5 * box.min()):
+        e1, f1, p1 = ew.real_images(x, q, box, 0.9, rc)
+        e2, f2, p2 = ew.real_minimage(x, q, box, 0.9, rc)
+        assert abs(e1 - e2) < 1e-12 * abs(e1)
+        assert np.abs(f1 - f2).max() < 1e-12 * np.abs(f1).max()
+        assert np.abs(p1 - p2).max() < 1e-12 * np.abs(p1).max()
+
+
+def test_real_space_pure_python_brute_force():
+    # tiny system, every image within the cutoff summed in plain Python
+    x, q, box = _small_system(seed=13, n=6, box=(3.0, 3.5, 4.0), min_dist=0.5)
+    alpha, rc = 0.8, 2.6   # rc > L/2: several images per pair, self-images too
+    e = 0.0
+    f = np.zeros((6, 3))
+    for i in range(6):
+        for j in range(6):
+            for a in range(-2, 3):
+                for b in range(-2, 3):
+                    for c in range(-2, 3):
+                        if i == j and a == b == c == 0:
+                            continue
+                        d = x[i] - x[j] + np.array([a, b, c]) * box
+                        r = math.sqrt(d @ d)
+                        if r >= rc:
+                            continue
+                        e += 0.5 * q[i] * q[j] * math.erfc(alpha * r) / r
+                        g = (math.erfc(alpha * r) / r + 2 * alpha / math.sqrt(math.pi) * math.exp(-(alpha * r) ** 2)) / (r * r)
+                        f[i] += q[i] * q[j] * g * d
+    e1, f1, _ = ew.real_images(x, q, box, alpha, rc)
+    assert abs(e - e1) < 1e-13 * max(1, abs(e))
+    assert np.abs(f - f1).max() < 1e-12 * max(1, np.abs(f).max())
+
+
+def test_replication_doubles_energy():
+    x, q, box = _small_system(seed=21, n=16, box=(6.0, 6.5, 5.0))
+    rc = 2.4
+    alpha = 3.5 / rc
+    r1 = ew.ewald(x, q, box, alpha, rc, tol=1e-18)
+    box2 = box * np.array([1, 1, 2])
+    x2 = np.concatenate([x, x + np.array([0, 0, box[2]])])
+    q2 = np.concatenate([q, q])
+    r2 = ew.ewald(x2, q2, box2, alpha, rc, tol=1e-18)
+    assert abs(r2["E"] - 2 * r1["E"]) < 1e-11 * abs(r1["E"])
+    assert np.abs(r2["F"][:16] - r1["F"]).max() < 1e-10 * np.abs(r1["F"]).max()
+    assert np.abs(r2["F"][16:] - r1["F"]).max() < 1e-10 * np.abs(r1["F"]).max()
+
+
+def test_translation_and_permutation_invariance():
+    x, q, box = _small_system(seed=31)
+    rc = 0.5 * box.min()
+    alpha = 3.2 / rc
+    r0 = ew.ewald(x, q, box, alpha, rc)
+    shift = np.array([0.37, -1.91, 4.2])
+    r1 = ew.ewald(x + shift, q, box, alpha, rc)
+    assert abs(r1["E"] - r0["E"]) < 1e-12 * abs(r0["E"])
+    assert np.abs(r1["F"] - r0["F"]).max() < 1e-10 * np.abs(r0["F"]).max()
+    perm = np.random.default_rng(0).permutation(len(q))
+    r2 = ew.ewald(x[perm], q[perm], box, alpha, rc)
+    assert abs(r2["E"] - r0["E"]) < 1e-12 * abs(r0["E"])
+    assert np.abs(r2["F"] - r0["F"][perm]).max() < 1e-10 * np.abs(r0["F"]).max()
+
+
+def test_k_sum_converged():
+    w = inputs.nacl()
+    a = ew.ewald(w.x, w.q, w.box, w.alpha, w.r_c, tol=1e-16)
+    b = ew.ewald(w.x, w.q, w.box, w.alpha, w.r_c, tol=1e-22)
+    assert abs(a["E"] - b["E"]) < 1e-14 * abs(b["E"])
+    assert np.abs(a["F"] - b["F"]).max() < 1e-12 * np.abs(b["F"]).max()
+
+
+def test_sampled_outputs_match_full():
+    x, q, box = _small_system(seed=41, n=40, box=(9.0, 9.0, 9.0), min_dist=0.5)
+    q[::5] = 0.0  # neutral sites still get a potential
+    rc = 4.0
+    full = ew.ewald(x, q, box, 0.8, rc)
+    s = np.array([0, 3, 5, 10, 39])
+    part = ew.ewald(x, q, box, 0.8, rc, sample=s)
+    assert part["E"] == pytest.approx(full["E"], rel=1e-13)
+    assert np.abs(part["F"] - full["F"][s]).max() < 1e-12 * np.abs(full["F"]).max()
+    assert np.abs(part["phi"] - full["phi"][s]).max() < 1e-12 * np.abs(full["phi"]).max()
+    assert np.all(part["F"][2] == 0.0)  # q=0 site feels no force
