@@ -1,0 +1,180 @@
+/*
+ * enuf.h -- C ABI of the ENUF hot path on AMD Instinct MI355X (gfx950).
+ *
+ * ENUF is Ewald summation whose reciprocal-space part is evaluated with
+ * non-uniform FFTs (paper Sec. 2.3).  For N point charges q_i at r_i in a
+ * periodic orthorhombic box (tin-foil boundary, Sec. 2.1) the library
+ * returns
+ *
+ *     E = E_R + E_K + E_self + E_bg,        F_i = -dE/dr_i
+ *
+ *   E_R    real-space erfc pair sum inside r_c (Eq. 17), forces from its
+ *          gradient (the corrected form of Eq. 29); pairs at distance 0
+ *          (coincident sites, whose Coulomb energy is infinite) are skipped;
+ *   E_K    reciprocal energy from the structure factor S(n) (Eq. 37-38),
+ *          S(n) computed by a type-1 ("transposed", Eq. 36) NFFT:
+ *          spread -> 3D FFT -> divide by the window transform;
+ *          forces from three type-2 ("conjugated", Eq. 35, 41-42) NFFTs;
+ *   E_self Gaussian self energy (Eq. 24, subtracted as in Eq. 25);
+ *   E_bg   neutralising-background energy -ke pi Q^2 / (2 V alpha^2), zero
+ *          for neutral systems (the paper assumes neutrality).
+ *
+ * Readings fixed by this library: the grid M is the FFT size per axis and all
+ * its modes except the Nyquist index -M/2 are kept (no oversampling); the
+ * window is the centred cardinal B-spline of order p (p grid points of
+ * support per axis) and the scaling step divides by its continuous Fourier
+ * transform sinc^p(pi n/M).
+ *
+ * Conventions for every call:
+ *  - Return value: ENUF_OK (0) or an error code; a failed call has no effect
+ *    on the context except the text behind enuf_last_error().
+ *  - Pointers named "device" must be device memory of the context's GPU
+ *    (e.g. a torch tensor's data_ptr()).  The caller owns all of them; the
+ *    library never frees caller memory.  The library owns its context and its
+ *    internal device workspace, released by enuf_destroy().
+ *  - "real" is double for ENUF_FP64 contexts and float for ENUF_FP32.
+ *  - Device work is enqueued on the context's HIP stream and is NOT
+ *    synchronised on return unless a call says so.  Calls on one context are
+ *    stream-ordered and not re-entrant (one host thread at a time).
+ */
+#ifndef ENUF_H
+#define ENUF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct enuf_ctx_s *enuf_ctx;
+
+typedef enum {
+    ENUF_OK = 0,
+    ENUF_EINVAL = 1,        /* invalid argument (NULL, size, parameter range) */
+    ENUF_ENOMEM = 2,        /* host or device allocation failed */
+    ENUF_EDEVICE = 3,       /* a HIP runtime call failed */
+    ENUF_ENONFINITE = 4,    /* non-finite position or charge seen on the device */
+    ENUF_ESTATE = 5,        /* call sequence error (e.g. grad before forward) */
+    ENUF_EUNSUPPORTED = 6   /* valid request outside what this build handles */
+} enuf_status;
+
+typedef enum { ENUF_FP64 = 0, ENUF_FP32 = 1 } enuf_precision;
+
+/* Options for enuf_set_option(). */
+typedef enum {
+    ENUF_OPT_KE = 0,          /* Coulomb prefactor 1/(4 pi eps0 eps_r); default 1 */
+    ENUF_OPT_TIMING = 1,      /* 1: record per-phase HIP event times; default 0 */
+    ENUF_OPT_GRAPH = 2,       /* 1: replay the launch sequence as a HIP graph; default 0 */
+    ENUF_OPT_CHECK = 3        /* 1: enuf_energy_forces synchronises and reports
+                                    ENUF_ENONFINITE itself; default 0 */
+} enuf_option;
+
+/* Internal buffers enuf_stage_copy() can read (for tests of single steps). */
+typedef enum {
+    ENUF_STAGE_GRID = 0,      /* spread output rho, real [Mz][My][Mx] */
+    ENUF_STAGE_SPECTRUM = 1,  /* forward 3D FFT of rho over (kx<Mx/2): complex
+                                 [Mz][My][Mx/2], the z transform not applied
+                                 (it happens fused with the influence step) */
+    ENUF_STAGE_FIELDS = 2,    /* real-space fields after the inverse FFTs, real
+                                 [Mz][My][Mx][4] = (E_x, E_y, E_z, psi) */
+    ENUF_STAGE_SORTED = 3,    /* int32 [N] permutation, grid-tile order
+                                 (entries past the active count are unused) */
+    ENUF_STAGE_COUNTS = 4,    /* int32 [2]: active particles, charged particles */
+    ENUF_STAGE_CELLS = 5      /* int32 [N] permutation, pair-cell order */
+} enuf_stage;
+
+/*
+ * enuf_create -- validate parameters and set up a context (paper Sec. 2.3:
+ * box, N, Ewald alpha, real-space cutoff r_c; Sec. 2.2: grid M and window).
+ *   out      receives the context (set to NULL on failure)
+ *   box      host double[3] box lengths (Lx, Ly, Lz) > 0
+ *   n        number of particles, 1 .. 2^28
+ *   alpha    Ewald splitting parameter > 0 (alpha = 1/(sqrt 2 sigma), Sec. 2.1)
+ *   r_c      real-space cutoff, 0 < r_c <= min(L)/2 (minimum image)
+ *   M        host int32[3] FFT grid (Mx, My, Mz); powers of two in [8, 1024]
+ *   p        window stencil width: 2, 4, 6 or 8, with 2p <= M_d for every axis
+ *   precision ENUF_FP64 or ENUF_FP32 (spread/FFT/gather/pair arithmetic;
+ *            energies are always reduced in double)
+ *   stream   hipStream_t to enqueue on (NULL = default stream)
+ * Allocates the device workspace (ENUF_ENOMEM on failure).  Selects the
+ * current HIP device as the context's device.
+ */
+enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double alpha,
+                        double r_c, const int32_t M[3], int32_t p, int32_t precision,
+                        void *stream);
+
+/* enuf_destroy -- free the context and its workspace.  NULL -> ENUF_EINVAL. */
+enuf_status enuf_destroy(enuf_ctx ctx);
+
+/* enuf_set_option -- set one enuf_option (value range checked). */
+enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value);
+
+/* enuf_set_stream -- enqueue later calls on another hipStream_t. */
+enuf_status enuf_set_stream(enuf_ctx ctx, void *stream);
+
+/*
+ * enuf_energy_forces -- one full evaluation (Sec. 3.2: real and reciprocal
+ * space on the GPU; forward NFFT for S(n) and the energy, Eq. 37-38; three
+ * inverse NFFTs packed into one pass for the forces, Eq. 41-42).
+ *   x    device real[N*3] positions, row-major (x,y,z); any values, wrapped
+ *        into the box; non-finite rows are excluded and flagged
+ *   q    device real[N] charges
+ *   E    device double[5] out: (total, E_R, E_K, E_self, E_bg)
+ *   F    device real[N*3] out forces, or NULL for energy only
+ *   phi  device real[N] out potentials phi_i = dE/dq_i, or NULL.  When
+ *        given, every particle (neutral ones too) gets its potential.
+ * The reciprocal forces are the ik-differentiated ones of Eq. 41-42, which
+ * sum to zero exactly; they approximate -dE/dr.  The exact gradient of the
+ * computed energy is available from enuf_energy_grad().  Non-finite input is
+ * recorded in a device flag read by enuf_get_flags() (or reported directly
+ * with ENUF_OPT_CHECK).
+ */
+enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, double *E,
+                               void *F, void *phi);
+
+/*
+ * enuf_energy_grad -- adjoint of the last enuf_energy_forces() on this
+ * context: the exact gradient of the energy E it computed, scaled by
+ * grad_E.  Uses the sorted particles and the potential grid kept from that
+ * call (x and q are not read again).
+ *   dEdx  device real[N*3] out: grad_E * dE/dr_i (window-derivative gather on
+ *         the potential grid, plus the real-space gradient), or NULL
+ *   dEdq  device real[N] out: grad_E * dE/dq_i, or NULL
+ * ENUF_ESTATE when no forward evaluation preceded it.
+ */
+enuf_status enuf_energy_grad(enuf_ctx ctx, double grad_E, void *dEdx, void *dEdq);
+
+/* enuf_get_flags -- synchronise the stream and return the sticky device
+ * flags (bit 0: non-finite input seen); clears them. */
+enuf_status enuf_get_flags(enuf_ctx ctx, int32_t *flags);
+
+/* enuf_stage_copy -- synchronously copy an internal buffer (enuf_stage) of
+ * the last evaluation into device memory dst of at least `bytes` bytes. */
+enuf_status enuf_stage_copy(enuf_ctx ctx, int32_t stage, void *dst, size_t bytes);
+
+/* enuf_stage_bytes -- size in bytes of an enuf_stage buffer. */
+enuf_status enuf_stage_bytes(enuf_ctx ctx, int32_t stage, size_t *bytes);
+
+/* enuf_get_timings -- per-phase milliseconds of the last evaluation when
+ * ENUF_OPT_TIMING is on (synchronises).  Fills up to n values in the order
+ * prep, sort, spread, fft_fwd, influence+z, fft_inv, gather, pair, finalize;
+ * *count receives the number of phases. */
+enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count);
+
+/* enuf_status_string -- static text for a status code. */
+const char *enuf_status_string(enuf_status s);
+
+/* enuf_last_error -- text of the last error on ctx (or of the last failed
+ * enuf_create when ctx is NULL); valid until the next call on ctx. */
+const char *enuf_last_error(enuf_ctx ctx);
+
+/* enuf_device_count -- number of visible HIP devices (0 without a GPU;
+ * never fails). */
+int32_t enuf_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENUF_H */

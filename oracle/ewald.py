@@ -44,6 +44,8 @@ def _load():
         d, i64, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
         lib.oracle_real_images.argtypes = [i64, vp, vp, vp, d, d, d, vp, vp, vp]
         lib.oracle_real_minimage.argtypes = [i64, vp, vp, vp, d, d, d, i64, vp, vp, vp, vp]
+        lib.oracle_real_minimage.restype = ctypes.c_int
+        lib.oracle_recip.restype = ctypes.c_int
         lib.oracle_recip.argtypes = [i64, vp, vp, vp, d, d, vp, d, i64, vp, vp, vp, vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -93,8 +95,10 @@ def real_minimage(x, q, box, alpha, rc, ke=1.0, sample=None):
     e = np.zeros(1)
     f = np.zeros((m, 3))
     phi = np.zeros(m)
-    _load().oracle_real_minimage(n, _p(x), _p(q), _p(box), alpha, rc, ke, ns, _p(sp),
-                                 _p(e), _p(f), _p(phi))
+    rc_ = _load().oracle_real_minimage(n, _p(x), _p(q), _p(box), alpha, rc, ke, ns, _p(sp),
+                                       _p(e), _p(f), _p(phi))
+    if rc_ != 0:
+        raise MemoryError("oracle_real_minimage: allocation failed")
     return float(e[0]), f, phi
 
 

@@ -108,13 +108,20 @@ int oracle_real_minimage(int64_t n, const double *x, const double *q,
                          double *e_out, double *f, double *phi) {
     double rc2 = rc * rc;
     double etot = 0.0;
+    /* only charged particles interact; list them once */
+    int64_t nq = 0;
+    for (int64_t i = 0; i < n; ++i) nq += (q[i] != 0.0);
+    int64_t *cid = (int64_t *)malloc(sizeof(int64_t) * (nq ? nq : 1));
+    if (!cid) return -1;
+    nq = 0;
+    for (int64_t i = 0; i < n; ++i) if (q[i] != 0.0) cid[nq++] = i;
     /* energy: all charged pairs i < j */
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : etot)
-    for (int64_t i = 0; i < n; ++i) {
-        if (q[i] == 0.0) continue;
+    for (int64_t a = 0; a < nq; ++a) {
+        int64_t i = cid[a];
         double ei = 0.0;
-        for (int64_t j = i + 1; j < n; ++j) {
-            if (q[j] == 0.0) continue;
+        for (int64_t b = a + 1; b < nq; ++b) {
+            int64_t j = cid[b];
             double d[3];
             for (int k = 0; k < 3; ++k) {
                 double t = x[3 * i + k] - x[3 * j + k];
@@ -134,8 +141,9 @@ int oracle_real_minimage(int64_t n, const double *x, const double *q,
     for (int64_t s = 0; s < ns; ++s) {
         int64_t i = nsample < 0 ? s : sample[s];
         double fi[3] = {0, 0, 0}, phii = 0.0, ei = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i || q[j] == 0.0) continue;
+        for (int64_t b = 0; b < nq; ++b) {
+            int64_t j = cid[b];
+            if (j == i) continue;
             double d[3];
             for (int k = 0; k < 3; ++k) {
                 double t = x[3 * i + k] - x[3 * j + k];
@@ -148,6 +156,7 @@ int oracle_real_minimage(int64_t n, const double *x, const double *q,
         if (f) { f[3 * s] = fi[0]; f[3 * s + 1] = fi[1]; f[3 * s + 2] = fi[2]; }
         if (phi) phi[s] = phii;
     }
+    free(cid);
     return 0;
 }
 

@@ -1,0 +1,1151 @@
+// enuf_kernels.hip -- HIP kernels of the ENUF hot path for gfx950 (CDNA4).
+//
+// One evaluation (paper Sec. 3.1-3.2) runs these phases on one stream:
+//   prep      wrap positions, bin keys, counting-sort ranks, charge sums
+//   sort      exclusive scan of the bins, scatter to tile / cell order
+//   spread    type-1 NFFT gridding step (Eq. 36): B-spline window, one
+//             workgroup per grid tile accumulating in LDS (no global atomics)
+//   fft_fwd   real-to-complex transform along x, complex along y (LDS pencils)
+//   z fused   forward z transform, scaling by the window transform (Eq. 37),
+//             influence function and FP64 energy (Eq. 38), the three ik field
+//             spectra of Eq. 41 plus the potential spectrum, inverse z
+//             transforms -- the spectrum never returns to HBM in between
+//   fft_inv   inverse y transforms, complex-to-real x transforms writing the
+//             four real fields interleaved (E_x, E_y, E_z, psi) per grid point
+//   gather    type-2 NFFT interpolation (Eq. 35, 42): all three force
+//             components and the potential in one pass
+//   pair      erfc real-space sum on a linked-cell list (Eq. 17, 29)
+//   finalize  energy parts in FP64, self (Eq. 24) and background terms
+#include "enuf_internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace enuf {
+
+// --------------------------------------------------------------------------
+// small types and helpers
+// --------------------------------------------------------------------------
+template <typename R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+template <typename R> using real4 = typename V4<R>::T;
+
+template <typename R> struct Cx { R x, y; };
+
+template <typename R> __device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __device__ __forceinline__ Cx<R> csub(Cx<R> a, Cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R> __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R> __device__ __forceinline__ Cx<R> cconj(Cx<R> a) { return {a.x, -a.y}; }
+// multiply by s*i (s = +1 or -1)
+template <typename R, int S> __device__ __forceinline__ Cx<R> cmuli(Cx<R> a) {
+  return S > 0 ? Cx<R>{-a.y, a.x} : Cx<R>{a.y, -a.x};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum over the block (blockDim.x a multiple of 64, <= 1024); result in thread 0.
+__device__ double block_sum(double v) {
+  __shared__ double red[16];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Periodic wrap of one coordinate into [0, L).  Positions already inside the
+// box pass through unchanged (bit for bit), so pair distances between them
+// carry no wrap rounding.
+template <typename R>
+__device__ __forceinline__ R wrap_pos(R x, R L, R invL) {
+  R xw = x;
+  if (!(xw >= R(0) && xw < L)) {
+    xw = x - L * floor(x * invL);
+    if (xw >= L) xw -= L;
+    if (xw < R(0)) xw += L;
+    if (!(xw >= R(0) && xw < L)) xw = R(0);
+  }
+  return xw;
+}
+
+// Grid coordinate s = x_w * M / L in [0, M) of a wrapped coordinate.
+template <typename R>
+__device__ __forceinline__ R grid_coord(R xw, R scale, int M) {
+  R s = xw * scale;
+  if (!(s < R(M))) s = R(0);  // x_w just below L rounding up to M is the point 0
+  return s;
+}
+
+__device__ __forceinline__ int wrapi(int i, int m) { return i < 0 ? i + m : (i >= m ? i - m : i); }
+
+// Cardinal B-spline of order P evaluated on a particle's P stencil points:
+// with f the fractional part of the grid coordinate, the stencil points are
+// floor(s) - P/2 + 1 + j and their weights w[j] = M_P(f + P - 1 - j), using
+// M_1 = 1 on [0,1) and M_n(y) = (y M_{n-1}(y) + (n - y) M_{n-1}(y - 1))/(n-1).
+// Built in place for increasing order; v[k] holds M_n(f + k).
+template <typename R, int P>
+__device__ __forceinline__ void bspline(R f, R (&w)[P]) {
+  R v[P];
+  v[0] = R(1);
+#pragma unroll
+  for (int n = 2; n <= P; ++n) {
+    const R inv = R(1) / R(n - 1);
+    v[n - 1] = (R(1) - f) * v[n - 2] * inv;
+#pragma unroll
+    for (int k = n - 2; k >= 1; --k) {
+      const R y = f + R(k);
+      v[k] = (y * v[k] + (R(n) - y) * v[k - 1]) * inv;
+    }
+    v[0] = f * v[0] * inv;
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) w[j] = v[P - 1 - j];
+}
+
+// Same, plus the derivative of each weight with respect to s:
+// M_P'(y) = M_{P-1}(y) - M_{P-1}(y - 1).
+template <typename R, int P>
+__device__ __forceinline__ void bspline_d(R f, R (&w)[P], R (&dw)[P]) {
+  R v[P];
+  v[0] = R(1);
+#pragma unroll
+  for (int n = 2; n <= P - 1; ++n) {
+    const R inv = R(1) / R(n - 1);
+    v[n - 1] = (R(1) - f) * v[n - 2] * inv;
+#pragma unroll
+    for (int k = n - 2; k >= 1; --k) {
+      const R y = f + R(k);
+      v[k] = (y * v[k] + (R(n) - y) * v[k - 1]) * inv;
+    }
+    v[0] = f * v[0] * inv;
+  }
+  // order P-1 values u[k] = M_{P-1}(f + k), k < P-1
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int k1 = P - 1 - j, k2 = P - 2 - j;  // u(k) = v[k] for 0 <= k <= P-2, else 0
+    R a = R(0), b = R(0);
+    if (k1 <= P - 2) a = v[k1];
+    if (k2 >= 0) b = v[k2];
+    dw[j] = a - b;
+  }
+  {
+    const int n = P;
+    const R inv = R(1) / R(n - 1);
+    v[n - 1] = (R(1) - f) * v[n - 2] * inv;
+#pragma unroll
+    for (int k = n - 2; k >= 1; --k) {
+      const R y = f + R(k);
+      v[k] = (y * v[k] + (R(n) - y) * v[k - 1]) * inv;
+    }
+    v[0] = f * v[0] * inv;
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) w[j] = v[P - 1 - j];
+}
+
+// --------------------------------------------------------------------------
+// fills
+// --------------------------------------------------------------------------
+__global__ void k_fill_i32(int *p, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+template <typename R>
+__global__ void k_fill_real(R *p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = R(0);
+}
+
+// --------------------------------------------------------------------------
+// prep: wrap, keys, counting-sort ranks, charge sums
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+                                                 int all_active, int *__restrict__ key_t,
+                                                 int *__restrict__ rank_t, int *__restrict__ key_c,
+                                                 int *__restrict__ rank_c, int *cnt_t, int *cnt_c,
+                                                 R *F, R *phi, double *qpart, int *counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double qs = 0.0, q2 = 0.0;
+  if (i < g.n) {
+    const R px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2], qi = q[i];
+    const bool fin = isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(qi);
+    if (!fin) atomicOr(&counts[2], 1);
+    const bool active = fin && (qi != R(0) || all_active);
+    if (fin) {
+      qs = (double)qi;
+      q2 = (double)qi * (double)qi;
+    }
+    if (active) {
+      const R p3[3] = {px, py, pz};
+      int tix[3], cix[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const R xw = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
+        const R sg = grid_coord(xw, R(g.M[d] / g.L[d]), g.M[d]);
+        tix[d] = (int)sg / g.T[d];
+        const int ci = (int)(xw * R(g.nc[d] / g.L[d]));
+        cix[d] = ci < g.nc[d] ? ci : g.nc[d] - 1;
+      }
+      const int neutral = (qi == R(0)) ? 1 : 0;
+      const int kt = 2 * ((tix[2] * g.nt[1] + tix[1]) * g.nt[0] + tix[0]) + neutral;
+      const int kc = 2 * ((cix[2] * g.nc[1] + cix[1]) * g.nc[0] + cix[0]) + neutral;
+      key_t[i] = kt;
+      key_c[i] = kc;
+      rank_t[i] = atomicAdd(&cnt_t[kt], 1);
+      rank_c[i] = atomicAdd(&cnt_c[kc], 1);
+    } else {
+      key_t[i] = -1;
+      key_c[i] = -1;
+      if (F) { F[3 * i] = R(0); F[3 * i + 1] = R(0); F[3 * i + 2] = R(0); }
+      if (phi) phi[i] = R(0);
+    }
+  }
+  const double a = block_sum(qs);
+  const double b = block_sum(q2);
+  if (threadIdx.x == 0) {
+    qpart[2 * blockIdx.x] = a;
+    qpart[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// Exclusive scan of cnt[0..len) in place, cnt[len] = total, by one block of
+// 1024 threads; returns (in *even_sum) the sum of the even-index counts.
+__device__ void block_exscan(int *cnt, int len, int *even_sum) {
+  __shared__ int part[1024];
+  __shared__ int evs[1024];
+  const int nt = blockDim.x, t = threadIdx.x;
+  const int chunk = (len + nt - 1) / nt;
+  const int lo = min(len, t * chunk), hi = min(len, lo + chunk);
+  int s = 0, ev = 0;
+  for (int i = lo; i < hi; ++i) {
+    s += cnt[i];
+    if ((i & 1) == 0) ev += cnt[i];
+  }
+  part[t] = s;
+  evs[t] = ev;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of part[]
+  for (int o = 1; o < nt; o <<= 1) {
+    int v = (t >= o) ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int i = lo; i < hi; ++i) {
+    const int c = cnt[i];
+    cnt[i] = run;
+    run += c;
+  }
+  if (t == nt - 1) cnt[len] = part[nt - 1];
+  __syncthreads();
+  if (t == 0) {
+    int e = 0;
+    for (int i = 0; i < nt; ++i) e += evs[i];
+    *even_sum = e;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan(int *off_t, int len_t, int *off_c, int len_c,
+                                               const double *qpart, int nqp, double *scal,
+                                               int *counts) {
+  __shared__ int ev;
+  if (blockIdx.x == 0) {
+    block_exscan(off_t, len_t, &ev);
+    if (threadIdx.x == 0) {
+      counts[0] = off_t[len_t];
+      counts[1] = ev;
+    }
+  } else if (blockIdx.x == 1) {
+    block_exscan(off_c, len_c, &ev);
+  } else {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nqp; i += blockDim.x) {
+      a += qpart[2 * i];
+      b += qpart[2 * i + 1];
+    }
+    a = block_sum(a);
+    b = block_sum(b);
+    if (threadIdx.x == 0) {
+      scal[0] = a;
+      scal[1] = b;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_scatter(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+                                                    const int *__restrict__ key_t, const int *__restrict__ rank_t,
+                                                    const int *__restrict__ key_c, const int *__restrict__ rank_c,
+                                                    const int *__restrict__ off_t, const int *__restrict__ off_c,
+                                                    real4<R> *part_t, int *perm_t, real4<R> *part_c, int *perm_c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int kt = key_t[i];
+  if (kt < 0) return;
+  const R px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2], qi = q[i];
+  const R p3[3] = {px, py, pz};
+  R xw[3], sg[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xw[d] = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
+    sg[d] = grid_coord(xw[d], R(g.M[d] / g.L[d]), g.M[d]);
+  }
+  const int pt = off_t[kt] + rank_t[i];
+  real4<R> a;
+  a.x = sg[0];
+  a.y = sg[1];
+  a.z = sg[2];
+  a.w = qi;
+  part_t[pt] = a;
+  perm_t[pt] = i;
+  const int pc = off_c[key_c[i]] + rank_c[i];
+  real4<R> b;
+  b.x = xw[0];
+  b.y = xw[1];
+  b.z = xw[2];
+  b.w = qi;
+  part_c[pc] = b;
+  perm_c[pc] = i;
+}
+
+// --------------------------------------------------------------------------
+// spread: rho_l = sum_i q_i B(s_i - l)   (type-1 gridding, Eq. 36)
+//
+// One workgroup owns one grid tile of T_x*T_y*T_z points and accumulates it in
+// LDS; it pulls every charged particle whose stencil reaches the tile from the
+// (up to) 27 neighbouring tiles' sorted ranges, so each grid point is written
+// exactly once, with no global atomics.  Staging: threads compute, for a batch
+// of candidates, the box of stencil points inside the tile and the 3*P window
+// weights (charge folded into z) into LDS; then each wavefront takes one staged
+// particle at a time and its 64 lanes sweep that particle's box.
+// --------------------------------------------------------------------------
+template <typename R, int P>
+__global__ __launch_bounds__(kBlock) void k_spread(const real4<R> *__restrict__ part,
+                                                   const int *__restrict__ off_t, Geom g,
+                                                   R *__restrict__ grid) {
+  __shared__ R acc[kMaxTilePts];
+  __shared__ R wst[kBlock][3][P];
+  __shared__ int box[kBlock][3];  // per axis: lstart | count << 8 | jstart << 16
+  __shared__ int rstart[27], rpre[28];
+  __shared__ int nrange, nstaged;
+
+  const int tid = threadIdx.x;
+  int t = blockIdx.x;
+  const int tx = t % g.nt[0];
+  t /= g.nt[0];
+  const int ty = t % g.nt[1];
+  const int tz = t / g.nt[1];
+  const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
+  const int tpts = g.T[0] * g.T[1] * g.T[2];
+  for (int e = tid; e < tpts; e += blockDim.x) acc[e] = R(0);
+
+  if (tid == 0) {
+    // neighbouring tiles (distinct ones only), charged sub-ranges
+    int offs[3][3], no[3];
+    const int tc[3] = {tx, ty, tz};
+    for (int d = 0; d < 3; ++d) {
+      if (g.nt[d] >= 3) { offs[d][0] = -1; offs[d][1] = 0; offs[d][2] = 1; no[d] = 3; }
+      else { offs[d][0] = 0; offs[d][1] = 1; no[d] = 2; }
+    }
+    int nr = 0, run = 0;
+    for (int a = 0; a < no[2]; ++a)
+      for (int b = 0; b < no[1]; ++b)
+        for (int c = 0; c < no[0]; ++c) {
+          const int nz = (tc[2] + offs[2][a] + g.nt[2]) % g.nt[2];
+          const int ny = (tc[1] + offs[1][b] + g.nt[1]) % g.nt[1];
+          const int nx = (tc[0] + offs[0][c] + g.nt[0]) % g.nt[0];
+          const int tt = (nz * g.nt[1] + ny) * g.nt[0] + nx;
+          const int s = off_t[2 * tt], e = off_t[2 * tt + 1];
+          rstart[nr] = s;
+          rpre[nr] = run;
+          run += e - s;
+          ++nr;
+        }
+    rpre[nr] = run;
+    nrange = nr;
+  }
+  __syncthreads();
+  const int total = rpre[nrange];
+  const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+
+  for (int base = 0; base < total; base += blockDim.x) {
+    if (tid == 0) nstaged = 0;
+    __syncthreads();
+    const int c = base + tid;
+    if (c < total) {
+      int r = 0;
+      while (rpre[r + 1] <= c) ++r;
+      const real4<R> v = part[rstart[r] + (c - rpre[r])];
+      const R s[3] = {v.x, v.y, v.z};
+      int ls[3], cnt[3], js[3];
+      R fr[3];
+      bool hit = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const R fl = floor(s[d]);
+        fr[d] = s[d] - fl;
+        int rel = (int)fl - P / 2 + 1 - t0[d];
+        rel = ((rel % g.M[d]) + g.M[d]) % g.M[d];
+        if (rel < g.T[d]) {
+          ls[d] = rel;
+          js[d] = 0;
+          cnt[d] = min(P, g.T[d] - rel);
+        } else {
+          ls[d] = 0;
+          js[d] = g.M[d] - rel;
+          cnt[d] = P - js[d];
+        }
+        hit = hit && cnt[d] > 0;
+      }
+      if (hit) {
+        const int slot = atomicAdd(&nstaged, 1);
+        R w[P];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          bspline<R, P>(fr[d], w);
+          const R sc = (d == 2) ? v.w : R(1);
+#pragma unroll
+          for (int j = 0; j < P; ++j) wst[slot][d][j] = w[j] * sc;
+          box[slot][d] = ls[d] | (cnt[d] << 8) | (js[d] << 16);
+        }
+      }
+    }
+    __syncthreads();
+    const int ns = nstaged;
+    for (int sp = wv; sp < ns; sp += nwv) {
+      const int bx = box[sp][0], by = box[sp][1], bz = box[sp][2];
+      const int lx = bx & 255, cx = (bx >> 8) & 255, jx = bx >> 16;
+      const int ly = by & 255, cy = (by >> 8) & 255, jy = by >> 16;
+      const int lz = bz & 255, cz = (bz >> 8) & 255, jz = bz >> 16;
+      const int cyx = cy * cx, npts = cz * cyx;
+      const float inv_yx = 1.0f / (float)cyx, inv_x = 1.0f / (float)cx;
+      for (int pt = lane; pt < npts; pt += 64) {
+        const int iz = (int)(((float)pt + 0.5f) * inv_yx);
+        const int rem = pt - iz * cyx;
+        const int iy = (int)(((float)rem + 0.5f) * inv_x);
+        const int ix = rem - iy * cx;
+        const R val = wst[sp][2][jz + iz] * wst[sp][1][jy + iy] * wst[sp][0][jx + ix];
+        atomicAdd(&acc[((lz + iz) * g.T[1] + (ly + iy)) * g.T[0] + (lx + ix)], val);
+      }
+    }
+    __syncthreads();
+  }
+  // write the tile (rows of T_x contiguous points)
+  for (int e = tid; e < tpts; e += blockDim.x) {
+    const int ix = e % g.T[0];
+    const int r = e / g.T[0];
+    const int iy = r % g.T[1];
+    const int iz = r / g.T[1];
+    grid[((size_t)(t0[2] + iz) * g.M[1] + (t0[1] + iy)) * g.M[0] + t0[0] + ix] = acc[e];
+  }
+}
+
+// --------------------------------------------------------------------------
+// FFT pencils in LDS: Stockham autosort, radix 4 (and one radix-2 stage for
+// odd powers of two), ping-pong between two LDS buffers.  Element i of pencil
+// f lives at buf[i*nb + f] so neighbouring lanes touch neighbouring words.
+// tw[m] = exp(-2 pi i m / n).  DIR = -1 forward, +1 inverse (unnormalised).
+// Returns the buffer holding the result.
+// --------------------------------------------------------------------------
+template <typename R, int DIR>
+__device__ Cx<R> *lds_fft(Cx<R> *a, Cx<R> *b, int n, int nb, const Cx<R> *__restrict__ tw) {
+  Cx<R> *src = a, *dst = b;
+  for (int Ns = 1; Ns < n;) {
+    const int Rdx = ((n / Ns) % 4 == 0) ? 4 : 2;
+    const int nbf = n / Rdx;
+    const int tws = n / (Ns * Rdx);
+    for (int w = threadIdx.x; w < nbf * nb; w += blockDim.x) {
+      const int f = w % nb, j = w / nb;
+      const int k = j & (Ns - 1);
+      const int ob = (j - k) * Rdx + k;
+      if (Rdx == 4) {
+        Cx<R> v0 = src[(j)*nb + f], v1 = src[(j + nbf) * nb + f];
+        Cx<R> v2 = src[(j + 2 * nbf) * nb + f], v3 = src[(j + 3 * nbf) * nb + f];
+        if (Ns > 1) {
+          Cx<R> w1 = tw[k * tws], w2 = tw[2 * k * tws], w3 = tw[3 * k * tws];
+          if (DIR > 0) { w1 = cconj(w1); w2 = cconj(w2); w3 = cconj(w3); }
+          v1 = cmul(v1, w1);
+          v2 = cmul(v2, w2);
+          v3 = cmul(v3, w3);
+        }
+        const Cx<R> s02 = cadd(v0, v2), d02 = csub(v0, v2);
+        const Cx<R> s13 = cadd(v1, v3), d13 = csub(v1, v3);
+        const Cx<R> id13 = cmuli<R, DIR>(d13);
+        dst[(ob)*nb + f] = cadd(s02, s13);
+        dst[(ob + Ns) * nb + f] = cadd(d02, id13);
+        dst[(ob + 2 * Ns) * nb + f] = csub(s02, s13);
+        dst[(ob + 3 * Ns) * nb + f] = csub(d02, id13);
+      } else {
+        Cx<R> v0 = src[(j)*nb + f], v1 = src[(j + nbf) * nb + f];
+        if (Ns > 1) {
+          Cx<R> w1 = tw[k * tws];
+          if (DIR > 0) w1 = cconj(w1);
+          v1 = cmul(v1, w1);
+        }
+        dst[(ob)*nb + f] = cadd(v0, v1);
+        dst[(ob + Ns) * nb + f] = csub(v0, v1);
+      }
+    }
+    __syncthreads();
+    Cx<R> *tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= Rdx;
+  }
+  return src;
+}
+
+// x pass, forward: each row of Mx reals -> bins 0 .. Mx/2-1 (the Nyquist bin
+// is not kept: those modes are outside the k-set).  The row is packed as
+// z_j = x_{2j} + i x_{2j+1}, transformed at length n = Mx/2 and untangled:
+// X_k = (Z_k + conj Z_{n-k})/2 - (i/2) e^{-2 pi i k/Mx} (Z_k - conj Z_{n-k}).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fft_x_r2c(const R *__restrict__ grid, Cx<R> *__restrict__ spec,
+                                                      Geom g, const Cx<R> *__restrict__ tw_n,
+                                                      const Cx<R> *__restrict__ tw_2n, int nb) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
+  const int n = g.M[0] / 2;
+  Cx<R> *B = A + n * nb;
+  const size_t row0 = (size_t)blockIdx.x * nb;
+  const Cx<R> *src = reinterpret_cast<const Cx<R> *>(grid) + row0 * n;
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int f = e / n, i = e % n;
+    A[i * nb + f] = src[(size_t)f * n + i];
+  }
+  __syncthreads();
+  Cx<R> *Z = lds_fft<R, -1>(A, B, n, nb, tw_n);
+  Cx<R> *dst = spec + row0 * n;
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int f = e / n, k = e % n;
+    const Cx<R> zk = Z[k * nb + f];
+    const Cx<R> zm = cconj(Z[((n - k) & (n - 1)) * nb + f]);
+    const Cx<R> s = cadd(zk, zm), d = csub(zk, zm);
+    const Cx<R> wd = cmul(tw_2n[k], d);
+    // X = s/2 - (i/2) w d
+    dst[(size_t)f * n + k] = Cx<R>{R(0.5) * (s.x + wd.y), R(0.5) * (s.y - wd.x)};
+  }
+}
+
+// Complex pencils along an axis of length n with element stride `inner`
+// (the contiguous dimension); a block takes nb consecutive pencils.
+// blockIdx.x: pencil block, blockIdx.y: outer index, blockIdx.z: component.
+template <typename R, int DIR>
+__global__ __launch_bounds__(kBlock) void k_fft_axis(Cx<R> *data, int n, int inner, size_t outer_stride,
+                                                     size_t comp_stride, const Cx<R> *__restrict__ tw,
+                                                     int nb) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
+  Cx<R> *B = A + n * nb;
+  Cx<R> *base = data + blockIdx.z * comp_stride + blockIdx.y * outer_stride + (size_t)blockIdx.x * nb;
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int f = e % nb, i = e / nb;
+    A[e] = base[(size_t)i * inner + f];
+  }
+  __syncthreads();
+  Cx<R> *res = lds_fft<R, DIR>(A, B, n, nb, tw);
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int f = e % nb, i = e / nb;
+    base[(size_t)i * inner + f] = res[e];
+  }
+}
+
+// z pass fused with the scaling and influence steps.  For each pencil
+// (kx, ky): forward transform along z; then for every mode n in the k-set
+//   g(n) = A(k) / c(n)^2,  A = exp(-k^2/4a^2)/k^2,  c = window transform,
+// energy += w_x g |rho^|^2 (w_x = 2 for kx > 0: the mirrored half),
+// field spectra E^_d = -i k_d g rho^ (d = x,y,z) and psi^ = g rho^, each
+// transformed back along z and written to fspec[d].
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec,
+                                                    Geom g, const Cx<R> *__restrict__ tw_z,
+                                                    const R *__restrict__ cwx, const R *__restrict__ cwy,
+                                                    const R *__restrict__ cwz, double *kpart, int nb) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n = g.M[2];
+  const int hx = g.M[0] / 2;
+  const int inner = hx * g.M[1];
+  const size_t half = (size_t)inner * n;
+  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
+  Cx<R> *B = A + n * nb;
+  Cx<R> *C = B + n * nb;
+  R *gk = reinterpret_cast<R *>(C + n * nb);
+  const int p0 = blockIdx.x * nb;
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int f = e % nb, i = e / nb;
+    A[e] = spec[(size_t)i * inner + p0 + f];
+  }
+  __syncthreads();
+  Cx<R> *S = lds_fft<R, -1>(A, B, n, nb, tw_z);
+  Cx<R> *P0 = (S == A) ? B : A;
+  Cx<R> *P1 = C;
+  const double twopi = 6.283185307179586476925286766559;
+  const double a4 = 1.0 / (4.0 * g.alpha * g.alpha);
+  double en = 0.0;
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int f = e % nb, kz = e / nb;
+    const int pidx = p0 + f;
+    const int kx = pidx % hx, ky = pidx / hx;
+    const int ny = ky < g.M[1] / 2 ? ky : ky - g.M[1];
+    const int nz = kz < n / 2 ? kz : kz - n;
+    const bool inK = (ky != g.M[1] / 2) && (kz != n / 2) && !(kx == 0 && ky == 0 && kz == 0);
+    R gv = R(0);
+    if (inK) {
+      const double kxv = twopi * kx / g.L[0], kyv = twopi * ny / g.L[1], kzv = twopi * nz / g.L[2];
+      const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
+      const R c = cwx[kx] * cwy[ky] * cwz[kz];
+      const R A_ = (R)(exp(-k2 * a4) / k2);
+      gv = A_ / (c * c);
+    }
+    gk[e] = gv;
+    const Cx<R> r = S[e];
+    en += (kx > 0 ? 2.0 : 1.0) * (double)gv * ((double)r.x * r.x + (double)r.y * r.y);
+  }
+  __syncthreads();
+  for (int o = 0; o < 4; ++o) {
+    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+      const int f = e % nb, kz = e / nb;
+      const Cx<R> r = S[e];
+      const R gv = gk[e];
+      Cx<R> out;
+      if (o < 3) {
+        const int pidx = p0 + f;
+        const int kx = pidx % hx, ky = pidx / hx;
+        int nd;
+        double Ld;
+        if (o == 0) { nd = kx; Ld = g.L[0]; }
+        else if (o == 1) { nd = ky < g.M[1] / 2 ? ky : ky - g.M[1]; Ld = g.L[1]; }
+        else { nd = kz < n / 2 ? kz : kz - n; Ld = g.L[2]; }
+        const R kd = (R)(twopi * nd / Ld) * gv;
+        // -i * kd * r
+        out = Cx<R>{kd * r.y, -kd * r.x};
+      } else {
+        out = Cx<R>{gv * r.x, gv * r.y};
+      }
+      P0[e] = out;
+    }
+    __syncthreads();
+    Cx<R> *res = lds_fft<R, 1>(P0, P1, n, nb, tw_z);
+    Cx<R> *dst = fspec + o * half;
+    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+      const int f = e % nb, i = e / nb;
+      dst[(size_t)i * inner + p0 + f] = res[e];
+    }
+    __syncthreads();
+  }
+  const double tot = block_sum(en);
+  if (threadIdx.x == 0) kpart[blockIdx.x] = tot;
+}
+
+// x pass, inverse, four components: bins 0 .. Mx/2-1 of each field (Nyquist
+// bin zero) -> Mx reals, written interleaved as real4 (E_x, E_y, E_z, psi).
+// Z_k = (X_k + conj X_{n-k}) + i e^{+2 pi i k/Mx} (X_k - conj X_{n-k}),
+// z = inverse transform (length n), x_{2j} = Re z_j, x_{2j+1} = Im z_j.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__ fspec, real4<R> *__restrict__ field,
+                                                       Geom g, const Cx<R> *__restrict__ tw_n,
+                                                       const Cx<R> *__restrict__ tw_2n, int nb) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n = g.M[0] / 2, Mx = g.M[0];
+  const size_t half = (size_t)n * g.M[1] * g.M[2];
+  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
+  Cx<R> *B = A + n * nb;
+  R *out = reinterpret_cast<R *>(B + n * nb);  // [nb][Mx][4]
+  const size_t row0 = (size_t)blockIdx.x * nb;
+  for (int o = 0; o < 4; ++o) {
+    const Cx<R> *src = fspec + o * half + row0 * n;
+    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+      const int f = e / n, k = e % n;
+      A[k * nb + f] = src[(size_t)f * n + k];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+      const int f = e % nb, k = e / nb;
+      const Cx<R> xk = A[k * nb + f];
+      const Cx<R> xm = (k == 0) ? Cx<R>{R(0), R(0)} : cconj(A[(n - k) * nb + f]);
+      const Cx<R> s = cadd(xk, xm), d = csub(xk, xm);
+      const Cx<R> wd = cmul(cconj(tw_2n[k]), d);
+      // s + i * wd
+      B[e] = Cx<R>{s.x - wd.y, s.y + wd.x};
+    }
+    __syncthreads();
+    Cx<R> *z = lds_fft<R, 1>(B, A, n, nb, tw_n);
+    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+      const int f = e % nb, j = e / nb;
+      const Cx<R> v = z[e];
+      out[((size_t)f * Mx + 2 * j) * 4 + o] = v.x;
+      out[((size_t)f * Mx + 2 * j + 1) * 4 + o] = v.y;
+    }
+    __syncthreads();
+  }
+  real4<R> *dst = field + row0 * Mx;
+  for (int e = threadIdx.x; e < nb * Mx; e += blockDim.x) {
+    real4<R> v;
+    v.x = out[4 * e];
+    v.y = out[4 * e + 1];
+    v.z = out[4 * e + 2];
+    v.w = out[4 * e + 3];
+    dst[e] = v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// gather: type-2 interpolation of the four fields (Eq. 35, 42), one thread per
+// active particle in tile order; results scattered to the caller's order.
+//   F_i   = pref q_i sum_l B(s_i - l) (E_x, E_y, E_z)_l,  pref = ke 4 pi / V
+//   phi_i = pref     sum_l B(s_i - l) psi_l
+// GRAD: exact gradient of the discrete energy instead,
+//   dE/dr_i,d = pref q_i (M_d/L_d) sum_l dB/ds_d psi_l,  dE/dq_i = phi_i.
+// --------------------------------------------------------------------------
+template <typename R, int P, bool GRAD>
+__global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restrict__ part,
+                                                         const int *__restrict__ perm,
+                                                         const int *__restrict__ counts, Geom g,
+                                                         const real4<R> *__restrict__ field, R pref, R gscale,
+                                                         R *__restrict__ vec_out, R *__restrict__ sca_out) {
+  // per-thread y/z weights live in LDS so the (z, y) row loop can stay rolled
+  // without indexing registers dynamically; only the x sweep is unrolled
+  __shared__ R wsh[kGatherBlock][GRAD ? 4 : 2][P];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= counts[0]) return;
+  R(*ws)[P] = wsh[threadIdx.x];
+  const real4<R> v = part[j];
+  const R s[3] = {v.x, v.y, v.z};
+  int b[3];
+  R wx[P], dx[P];
+  {
+    R wy[P], wz[P], dy[P], dz[P];
+    R fl = floor(s[0]);
+    b[0] = (int)fl - P / 2 + 1;
+    if (GRAD) bspline_d<R, P>(s[0] - fl, wx, dx); else bspline<R, P>(s[0] - fl, wx);
+    fl = floor(s[1]);
+    b[1] = (int)fl - P / 2 + 1;
+    if (GRAD) bspline_d<R, P>(s[1] - fl, wy, dy); else bspline<R, P>(s[1] - fl, wy);
+    fl = floor(s[2]);
+    b[2] = (int)fl - P / 2 + 1;
+    if (GRAD) bspline_d<R, P>(s[2] - fl, wz, dz); else bspline<R, P>(s[2] - fl, wz);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      ws[0][k] = wy[k];
+      ws[1][k] = wz[k];
+      if (GRAD) {
+        ws[2][k] = dy[k];
+        ws[3][k] = dz[k];
+      }
+    }
+  }
+  int gx[P];
+#pragma unroll
+  for (int jx = 0; jx < P; ++jx) gx[jx] = wrapi(b[0] + jx, g.M[0]);
+  R a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 2
+  for (int r = 0; r < P * P; ++r) {
+    const int jz = r / P, jy = r - jz * P;
+    const int gz = wrapi(b[2] + jz, g.M[2]);
+    const int gy = wrapi(b[1] + jy, g.M[1]);
+    const real4<R> *row = field + ((size_t)gz * g.M[1] + gy) * g.M[0];
+    if (!GRAD) {
+      const R wzy = ws[1][jz] * ws[0][jy];
+#pragma unroll
+      for (int jx = 0; jx < P; ++jx) {
+        const real4<R> f = row[gx[jx]];
+        const R w = wzy * wx[jx];
+        a0 += w * f.x;
+        a1 += w * f.y;
+        a2 += w * f.z;
+        a3 += w * f.w;
+      }
+    } else {
+      const R wz_ = ws[1][jz], wy_ = ws[0][jy], dz_ = ws[3][jz], dy_ = ws[2][jy];
+      const R wzy = wz_ * wy_, dzy = dz_ * wy_, wzdy = wz_ * dy_;
+#pragma unroll
+      for (int jx = 0; jx < P; ++jx) {
+        const R psi = row[gx[jx]].w;
+        a0 += wzy * dx[jx] * psi;
+        a1 += wzdy * wx[jx] * psi;
+        a2 += dzy * wx[jx] * psi;
+        a3 += wzy * wx[jx] * psi;
+      }
+    }
+  }
+  const int i = perm[j];
+  const R qi = v.w;
+  if (!GRAD) {
+    if (vec_out) {
+      vec_out[3 * i] = pref * qi * a0;
+      vec_out[3 * i + 1] = pref * qi * a1;
+      vec_out[3 * i + 2] = pref * qi * a2;
+    }
+    if (sca_out) sca_out[i] = pref * a3;
+  } else {
+    if (vec_out) {
+      const R c = gscale * pref * qi;
+      vec_out[3 * i] = c * R(g.M[0] / g.L[0]) * a0;
+      vec_out[3 * i + 1] = c * R(g.M[1] / g.L[1]) * a1;
+      vec_out[3 * i + 2] = c * R(g.M[2] / g.L[2]) * a2;
+    }
+    if (sca_out) sca_out[i] = gscale * pref * a3;
+  }
+}
+
+// --------------------------------------------------------------------------
+// real-space pair sum on a linked-cell list (Eq. 17; gradient form of Eq. 29)
+// Thread per active particle (cell order); neighbour cells' charged ranges are
+// read directly (lanes of one wave share cells, so loads hit in cache).  Both
+// orderings of a pair are evaluated, so no atomics are needed.
+//   MODE 0: out_vec (forces) += ke q_i f_i, out_sca (potential) += ke phi_i +
+//           self + background terms, energy partials.
+//   MODE 1: adjoint, out_vec (dE/dr) -= gscale ke q_i f_i, out_sca (dE/dq) +=
+//           gscale (ke phi_i + self + background).
+// --------------------------------------------------------------------------
+template <typename R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_pair(const real4<R> *__restrict__ part, const int *__restrict__ perm,
+                                                 const int *__restrict__ off_c, const int *__restrict__ counts,
+                                                 Geom g, const double *__restrict__ scal, R gscale,
+                                                 R *__restrict__ out_vec, R *__restrict__ out_sca,
+                                                 double *rpart) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (j < counts[0]) {
+    const real4<R> v = part[j];
+    const R xi = v.x, yi = v.y, zi = v.z, qi = v.w;
+    const R L0 = (R)g.L[0], L1 = (R)g.L[1], L2 = (R)g.L[2];
+    const R iL0 = (R)(1.0 / g.L[0]), iL1 = (R)(1.0 / g.L[1]), iL2 = (R)(1.0 / g.L[2]);
+    const R rc2 = (R)(g.rc * g.rc);
+    const R al = (R)g.alpha, al2 = (R)(g.alpha * g.alpha);
+    const R c2a = (R)(2.0 * g.alpha / 1.7724538509055160272981674833411);
+    int cc[3];
+    const R pos[3] = {xi, yi, zi};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int c = (int)(pos[d] * R(g.nc[d] / g.L[d]));  // same expression as k_prep
+      cc[d] = c < g.nc[d] ? c : g.nc[d] - 1;
+    }
+    int no[3], o0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (g.nc[d] >= 3) { no[d] = 3; o0[d] = -1; }
+      else { no[d] = g.nc[d]; o0[d] = 0; }
+    }
+    R fx = 0, fy = 0, fz = 0, ph = 0;
+    for (int a = 0; a < no[2]; ++a) {
+      const int cz = (cc[2] + o0[2] + a + g.nc[2]) % g.nc[2];
+      for (int b = 0; b < no[1]; ++b) {
+        const int cy = (cc[1] + o0[1] + b + g.nc[1]) % g.nc[1];
+        for (int c = 0; c < no[0]; ++c) {
+          const int cx = (cc[0] + o0[0] + c + g.nc[0]) % g.nc[0];
+          const int cid = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+          const int s = off_c[2 * cid], t = off_c[2 * cid + 1];
+          for (int k = s; k < t; ++k) {
+            const real4<R> u = part[k];
+            R ddx = xi - u.x, ddy = yi - u.y, ddz = zi - u.z;
+            ddx -= L0 * rint(ddx * iL0);
+            ddy -= L1 * rint(ddy * iL1);
+            ddz -= L2 * rint(ddz * iL2);
+            const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (r2 < rc2 && r2 > R(0)) {
+              const R r = sqrt(r2);
+              const R ir = R(1) / r;
+              const R ec = erfc(al * r) * ir;
+              const R fs = u.w * (ec + c2a * exp(-al2 * r2)) * ir * ir;
+              ph += u.w * ec;
+              fx += fs * ddx;
+              fy += fs * ddy;
+              fz += fs * ddz;
+            }
+          }
+        }
+      }
+    }
+    const double ke = g.ke;
+    e = 0.5 * (double)qi * (double)ph;
+    const int i = perm[j];
+    const double V = g.L[0] * g.L[1] * g.L[2];
+    const double phs = ke * (double)ph - 2.0 * ke * g.alpha / 1.7724538509055160272981674833411 * (double)qi -
+                       ke * 3.14159265358979323846 * scal[0] / (V * g.alpha * g.alpha);
+    if (MODE == 0) {
+      if (out_vec) {
+        const R c = (R)ke * qi;
+        out_vec[3 * i] += c * fx;
+        out_vec[3 * i + 1] += c * fy;
+        out_vec[3 * i + 2] += c * fz;
+      }
+      if (out_sca) out_sca[i] += (R)phs;
+    } else {
+      if (out_vec) {
+        const R c = -gscale * (R)ke * qi;
+        out_vec[3 * i] += c * fx;
+        out_vec[3 * i + 1] += c * fy;
+        out_vec[3 * i + 2] += c * fz;
+      }
+      if (out_sca) out_sca[i] += gscale * (R)phs;
+    }
+  }
+  if (MODE == 0) {
+    const double tot = block_sum(e);
+    if (threadIdx.x == 0) rpart[blockIdx.x] = tot;
+  }
+}
+
+// energy parts in FP64: (total, E_R, E_K, E_self, E_bg)
+__global__ __launch_bounds__(256) void k_finalize(const double *kpart, int nk, const double *rpart, int nr,
+                                                  const double *scal, Geom g, double *E) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nk; i += blockDim.x) a += kpart[i];
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) b += rpart[i];
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) {
+    const double pi = 3.14159265358979323846;
+    const double V = g.L[0] * g.L[1] * g.L[2];
+    const double ek = g.ke * 2.0 * pi / V * a;
+    const double er = g.ke * b;
+    const double es = -g.ke * g.alpha / 1.7724538509055160272981674833411 * scal[1];
+    const double eb = -g.ke * pi * scal[0] * scal[0] / (2.0 * V * g.alpha * g.alpha);
+    E[0] = er + ek + es + eb;
+    E[1] = er;
+    E[2] = ek;
+    E[3] = es;
+    E[4] = eb;
+  }
+}
+
+// --------------------------------------------------------------------------
+// host side: tables and launch sequences
+// --------------------------------------------------------------------------
+int nblk_prep(const Geom &g) { return (g.n + kBlock - 1) / kBlock; }
+int nblk_pair(const Geom &g) { return (g.n + kBlock - 1) / kBlock; }
+
+// pencils per block for a pass so that `per_pencil` bytes * nb <= budget,
+// nb a power of two dividing `count`, at most 16
+static int pick_nb(size_t per_pencil, size_t budget, int count) {
+  int nb = 16;
+  while (nb > 1 && ((size_t)nb * per_pencil > budget || count % nb != 0)) nb >>= 1;
+  return nb;
+}
+
+static int nb_xr2c(const Geom &g, size_t cs) { return pick_nb(2 * (g.M[0] / 2) * cs, 32768, g.M[1] * g.M[2]); }
+static int nb_axis(int n, int inner, size_t cs) { return pick_nb(2 * (size_t)n * cs, 32768, inner); }
+static int nb_z(const Geom &g, size_t cs) {
+  return pick_nb((size_t)g.M[2] * (3 * cs + cs / 2), 61440, (g.M[0] / 2) * g.M[1]);
+}
+static int nb_xc2r(const Geom &g, size_t cs) {
+  const int n = g.M[0] / 2;
+  return pick_nb((size_t)n * (2 * cs) + (size_t)g.M[0] * 4 * (cs / 2), 49152, g.M[1] * g.M[2]);
+}
+
+int nblk_z(const Geom &g, bool fp64) {
+  const size_t cs = fp64 ? 16 : 8;
+  return (g.M[0] / 2) * g.M[1] / nb_z(g, cs);
+}
+
+// table layout (in reals): [0] tw x-half (n=Mx/2) complex, [1] tw e^{-2pi i k/Mx}
+// k<Mx/2 complex, [2] tw y complex, [3] tw z complex, [4] c_x (Mx/2 reals),
+// [5] c_y (My), [6] c_z (Mz)
+size_t table_size(const Geom &g, size_t off[8]) {
+  size_t o = 0;
+  off[0] = o; o += 2 * (g.M[0] / 2);
+  off[1] = o; o += 2 * (g.M[0] / 2);
+  off[2] = o; o += 2 * g.M[1];
+  off[3] = o; o += 2 * g.M[2];
+  off[4] = o; o += g.M[0] / 2;
+  off[5] = o; o += g.M[1];
+  off[6] = o; o += g.M[2];
+  off[7] = o;
+  return o;
+}
+
+template <typename R>
+void fill_tables(const Geom &g, const size_t off[8], R *h) {
+  const double pi = 3.14159265358979323846;
+  auto tw = [&](R *dst, int n, int period) {
+    for (int m = 0; m < n; ++m) {
+      const double a = -2.0 * pi * (double)m / (double)period;
+      dst[2 * m] = (R)std::cos(a);
+      dst[2 * m + 1] = (R)std::sin(a);
+    }
+  };
+  tw(h + off[0], g.M[0] / 2, g.M[0] / 2);
+  tw(h + off[1], g.M[0] / 2, g.M[0]);
+  tw(h + off[2], g.M[1], g.M[1]);
+  tw(h + off[3], g.M[2], g.M[2]);
+  // window transform sinc^p(pi n / M), n signed
+  auto cw = [&](R *dst, int cnt, int M) {
+    for (int k = 0; k < cnt; ++k) {
+      const int nn = k < M / 2 ? k : k - M;
+      const double t = pi * (double)nn / (double)M;
+      const double s = nn == 0 ? 1.0 : std::sin(t) / t;
+      dst[k] = (R)std::pow(s, g.p);
+    }
+  };
+  cw(h + off[4], g.M[0] / 2, g.M[0]);
+  cw(h + off[5], g.M[1], g.M[1]);
+  cw(h + off[6], g.M[2], g.M[2]);
+}
+template void fill_tables<float>(const Geom &, const size_t[8], float *);
+template void fill_tables<double>(const Geom &, const size_t[8], double *);
+
+#define ENUF_TRY(x)                   \
+  do {                                \
+    hipError_t e_ = (x);              \
+    if (e_ != hipSuccess) return e_;  \
+  } while (0)
+
+template <typename R, int P>
+static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
+  hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(kBlock), 0, st,
+                     (const real4<R> *)w.part_t, w.off_t, g, (R *)w.grid);
+}
+template <typename R, int P>
+static void launch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R *vo, R *so,
+                          bool grad) {
+  const int nb = (g.n + kGatherBlock - 1) / kGatherBlock;
+  if (grad)
+    hipLaunchKernelGGL((k_gather<R, P, true>), dim3(nb), dim3(kGatherBlock), 0, st, (const real4<R> *)w.part_t,
+                       w.perm_t, w.counts, g, (const real4<R> *)w.field, pref, gs, vo, so);
+  else
+    hipLaunchKernelGGL((k_gather<R, P, false>), dim3(nb), dim3(kGatherBlock), 0, st, (const real4<R> *)w.part_t,
+                       w.perm_t, w.counts, g, (const real4<R> *)w.field, pref, gs, vo, so);
+}
+
+template <typename R>
+static void dispatch_spread(const Geom &g, const Work &w, hipStream_t st) {
+  switch (g.p) {
+    case 2: launch_spread<R, 2>(g, w, st); break;
+    case 4: launch_spread<R, 4>(g, w, st); break;
+    case 6: launch_spread<R, 6>(g, w, st); break;
+    default: launch_spread<R, 8>(g, w, st); break;
+  }
+}
+template <typename R>
+static void dispatch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R *vo, R *so, bool grad) {
+  switch (g.p) {
+    case 2: launch_gather<R, 2>(g, w, st, pref, gs, vo, so, grad); break;
+    case 4: launch_gather<R, 4>(g, w, st, pref, gs, vo, so, grad); break;
+    case 6: launch_gather<R, 6>(g, w, st, pref, gs, vo, so, grad); break;
+    default: launch_gather<R, 8>(g, w, st, pref, gs, vo, so, grad); break;
+  }
+}
+
+template <typename R>
+hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R *x, const R *q, double *E,
+                          R *F, R *phi, bool all_active, hipEvent_t *ev) {
+  const size_t cs = sizeof(Cx<R>);
+  const R *tab = (const R *)w.tables;
+  const Cx<R> *tw_xh = (const Cx<R> *)(tab + w.tab_off[0]);
+  const Cx<R> *tw_x2 = (const Cx<R> *)(tab + w.tab_off[1]);
+  const Cx<R> *tw_y = (const Cx<R> *)(tab + w.tab_off[2]);
+  const Cx<R> *tw_z = (const Cx<R> *)(tab + w.tab_off[3]);
+  const R *cwx = tab + w.tab_off[4], *cwy = tab + w.tab_off[5], *cwz = tab + w.tab_off[6];
+  const int hx = g.M[0] / 2;
+  const size_t halfG = (size_t)hx * g.M[1] * g.M[2];
+  auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
+
+  mark(0);
+  // prep
+  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(kBlock), 0, st, w.off_t, 2 * g.ntiles + 1, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(kBlock), 0, st, w.off_c, 2 * g.ncells + 1, 0);
+  hipLaunchKernelGGL((k_prep<R>), dim3(nblk_prep(g)), dim3(kBlock), 0, st, x, q, g, all_active ? 1 : 0,
+                     w.key_t, w.rank_t, w.key_c, w.rank_c, w.off_t, w.off_c, F, phi, w.qpart, w.counts);
+  ENUF_TRY(hipGetLastError());
+  mark(1);
+  // sort
+  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, st, w.off_t, 2 * g.ntiles, w.off_c, 2 * g.ncells,
+                     (const double *)w.qpart, nblk_prep(g), w.scal, w.counts);
+  hipLaunchKernelGGL((k_scatter<R>), dim3(nblk_prep(g)), dim3(kBlock), 0, st, x, q, g, w.key_t, w.rank_t,
+                     w.key_c, w.rank_c, w.off_t, w.off_c, (real4<R> *)w.part_t, w.perm_t,
+                     (real4<R> *)w.part_c, w.perm_c);
+  ENUF_TRY(hipGetLastError());
+  mark(2);
+  // spread
+  dispatch_spread<R>(g, w, st);
+  ENUF_TRY(hipGetLastError());
+  mark(3);
+  // forward x (r2c), y
+  {
+    const int nb = nb_xr2c(g, cs);
+    hipLaunchKernelGGL((k_fft_x_r2c<R>), dim3(g.M[1] * g.M[2] / nb), dim3(kBlock), 2 * hx * nb * cs, st,
+                       (const R *)w.grid, (Cx<R> *)w.spec, g, tw_xh, tw_x2, nb);
+    const int nby = nb_axis(g.M[1], hx, cs);
+    hipLaunchKernelGGL((k_fft_axis<R, -1>), dim3(hx / nby, g.M[2], 1), dim3(kBlock), 2 * g.M[1] * nby * cs,
+                       st, (Cx<R> *)w.spec, g.M[1], hx, (size_t)hx * g.M[1], (size_t)0, tw_y, nby);
+  }
+  ENUF_TRY(hipGetLastError());
+  mark(4);
+  // z fused: forward z, influence, energy, four inverse z
+  {
+    const int nb = nb_z(g, cs);
+    const size_t sh = (size_t)g.M[2] * nb * (3 * cs + sizeof(R));
+    hipLaunchKernelGGL((k_z_fused<R>), dim3(hx * g.M[1] / nb), dim3(kBlock), sh, st,
+                       (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, tw_z, cwx, cwy, cwz, w.kpart, nb);
+  }
+  ENUF_TRY(hipGetLastError());
+  mark(5);
+  // inverse y (4 components), inverse x c2r -> interleaved fields
+  {
+    const int nby = nb_axis(g.M[1], hx, cs);
+    hipLaunchKernelGGL((k_fft_axis<R, 1>), dim3(hx / nby, g.M[2], 4), dim3(kBlock), 2 * g.M[1] * nby * cs,
+                       st, (Cx<R> *)w.fspec, g.M[1], hx, (size_t)hx * g.M[1], halfG, tw_y, nby);
+    const int nb = nb_xc2r(g, cs);
+    const size_t sh = 2 * (size_t)hx * nb * cs + (size_t)nb * g.M[0] * 4 * sizeof(R);
+    hipLaunchKernelGGL((k_fft_x_c2r4<R>), dim3(g.M[1] * g.M[2] / nb), dim3(kBlock), sh, st,
+                       (const Cx<R> *)w.fspec, (real4<R> *)w.field, g, tw_xh, tw_x2, nb);
+  }
+  ENUF_TRY(hipGetLastError());
+  mark(6);
+  // gather
+  const double V = g.L[0] * g.L[1] * g.L[2];
+  const R pref = (R)(g.ke * 4.0 * 3.14159265358979323846 / V);
+  if (F || phi) dispatch_gather<R>(g, w, st, pref, R(1), F, phi, false);
+  ENUF_TRY(hipGetLastError());
+  mark(7);
+  // pair
+  hipLaunchKernelGGL((k_pair<R, 0>), dim3(nblk_pair(g)), dim3(kBlock), 0, st, (const real4<R> *)w.part_c,
+                     w.perm_c, w.off_c, w.counts, g, w.scal, R(1), F, phi, w.rpart);
+  ENUF_TRY(hipGetLastError());
+  mark(8);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double *)w.kpart,
+                     nblk_z(g, sizeof(R) == 8), (const double *)w.rpart, nblk_pair(g), (const double *)w.scal, g,
+                     E);
+  ENUF_TRY(hipGetLastError());
+  mark(9);
+  return hipSuccess;
+}
+
+template <typename R>
+hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double gscale, R *dEdx, R *dEdq) {
+  if (dEdx) hipLaunchKernelGGL((k_fill_real<R>), dim3(256), dim3(kBlock), 0, st, dEdx, 3LL * g.n);
+  if (dEdq) hipLaunchKernelGGL((k_fill_real<R>), dim3(256), dim3(kBlock), 0, st, dEdq, (long long)g.n);
+  ENUF_TRY(hipGetLastError());
+  const double V = g.L[0] * g.L[1] * g.L[2];
+  const R pref = (R)(g.ke * 4.0 * 3.14159265358979323846 / V);
+  dispatch_gather<R>(g, w, st, pref, (R)gscale, dEdx, dEdq, true);
+  ENUF_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_pair<R, 1>), dim3(nblk_pair(g)), dim3(kBlock), 0, st, (const real4<R> *)w.part_c,
+                     w.perm_c, w.off_c, w.counts, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
+  return hipGetLastError();
+}
+
+template hipError_t launch_forward<float>(const Geom &, const Work &, hipStream_t, const float *, const float *,
+                                          double *, float *, float *, bool, hipEvent_t *);
+template hipError_t launch_forward<double>(const Geom &, const Work &, hipStream_t, const double *,
+                                           const double *, double *, double *, double *, bool, hipEvent_t *);
+template hipError_t launch_adjoint<float>(const Geom &, const Work &, hipStream_t, double, float *, float *);
+template hipError_t launch_adjoint<double>(const Geom &, const Work &, hipStream_t, double, double *, double *);
+
+}  // namespace enuf

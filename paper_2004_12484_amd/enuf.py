@@ -1,0 +1,222 @@
+"""Python binding of the ENUF HIP library (``libenuf.so``, C ABI in
+``include/enuf.h``).
+
+Argument marshalling only: every step of an evaluation runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors are passed by
+``data_ptr()``) and the stream (``torch.cuda.current_stream()``).  There is no
+CPU fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libenuf.so")
+
+ENUF_OK, ENUF_EINVAL, ENUF_ENOMEM, ENUF_EDEVICE, ENUF_ENONFINITE, ENUF_ESTATE, ENUF_EUNSUPPORTED = range(7)
+ENUF_FP64, ENUF_FP32 = 0, 1
+OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK = 0, 1, 2, 3
+STAGE_GRID, STAGE_SPECTRUM, STAGE_FIELDS, STAGE_SORTED, STAGE_COUNTS, STAGE_CELLS = range(6)
+PHASES = ("prep", "sort", "spread", "fft_fwd", "influence_z", "fft_inv", "gather", "pair", "finalize")
+
+# every symbol include/enuf.h declares
+EXPORTS = (
+    "enuf_create", "enuf_destroy", "enuf_set_option", "enuf_set_stream", "enuf_energy_forces",
+    "enuf_energy_grad", "enuf_get_flags", "enuf_stage_copy", "enuf_stage_bytes", "enuf_get_timings",
+    "enuf_status_string", "enuf_last_error", "enuf_device_count",
+)
+
+_lib = None
+
+
+class EnufError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"ENUF error {status}: {message}")
+        self.status = status
+
+
+def load_library():
+    """Load libenuf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"ENUF HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -m paper_2004_12484_amd.build`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.enuf_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(d), i64, d, d, ctypes.POINTER(i32), i32, i32, vp]
+    lib.enuf_destroy.argtypes = [vp]
+    lib.enuf_set_option.argtypes = [vp, i32, d]
+    lib.enuf_set_stream.argtypes = [vp, vp]
+    lib.enuf_energy_forces.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.enuf_energy_grad.argtypes = [vp, d, vp, vp]
+    lib.enuf_get_flags.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.enuf_stage_copy.argtypes = [vp, i32, vp, sz]
+    lib.enuf_stage_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    lib.enuf_get_timings.argtypes = [vp, ctypes.POINTER(d), i32, ctypes.POINTER(i32)]
+    lib.enuf_status_string.argtypes = [i32]
+    lib.enuf_status_string.restype = ctypes.c_char_p
+    lib.enuf_last_error.argtypes = [vp]
+    lib.enuf_last_error.restype = ctypes.c_char_p
+    lib.enuf_device_count.restype = i32
+    for name in EXPORTS:
+        if name not in ("enuf_status_string", "enuf_last_error", "enuf_device_count"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status, handle=None):
+    if status != ENUF_OK:
+        lib = load_library()
+        msg = lib.enuf_last_error(handle).decode(errors="replace")
+        raise EnufError(status, msg or lib.enuf_status_string(status).decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Enuf:
+    """One ENUF context: fixed box, particle count, parameters and precision.
+
+    Positions/charges/outputs are CUDA (HIP) tensors of dtype float64
+    (precision "f64") or float32 ("f32"); energies are always float64.
+    """
+
+    def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("ENUF needs a HIP GPU; torch.cuda.is_available() is False")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if dev.type != "cuda":
+            raise ValueError(f"ENUF runs on a HIP device, got {dev}")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.n = int(n)
+        self.box = tuple(float(b) for b in box)
+        self.alpha, self.r_c, self.p = float(alpha), float(r_c), int(p)
+        self.M = tuple(int(m) for m in (M if hasattr(M, "__len__") else (M, M, M)))
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+            boxa = (ctypes.c_double * 3)(*self.box)
+            Ma = (ctypes.c_int32 * 3)(*self.M)
+            st = lib.enuf_create(ctypes.byref(self._h), boxa, self.n, self.alpha, self.r_c, Ma, self.p,
+                                 ENUF_FP64 if precision == "f64" else ENUF_FP32, ctypes.c_void_p(stream))
+            if st != ENUF_OK:
+                msg = lib.enuf_last_error(None).decode(errors="replace")
+                raise EnufError(st, msg)
+        if ke != 1.0:
+            self.set_option(OPT_KE, ke)
+        if check:
+            self.set_option(OPT_CHECK, 1)
+        self._E = torch.zeros(5, dtype=torch.float64, device=self.device)
+
+    # -- plumbing ---------------------------------------------------------
+    def set_option(self, opt, value):
+        _check(load_library().enuf_set_option(self._h, int(opt), float(value)), self._h)
+
+    def _bind_stream(self):
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().enuf_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+
+    def _in(self, t, shape):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != self.dtype:
+            raise TypeError(f"expected a {self.dtype} tensor on {self.device}")
+        if tuple(t.shape) != shape:
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return t.contiguous()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().enuf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- evaluation -------------------------------------------------------
+    def energy_forces(self, x, q, forces=True, potential=False, out=None):
+        """Returns (E, F, phi): E float64[5] = (total, real, reciprocal, self,
+        background); F [N,3] or None; phi [N] (dE/dq) or None."""
+        x = self._in(x, (self.n, 3))
+        q = self._in(q, (self.n,))
+        self._bind_stream()
+        E = torch.empty(5, dtype=torch.float64, device=self.device) if out is None else out
+        F = torch.empty((self.n, 3), dtype=self.dtype, device=self.device) if forces else None
+        phi = torch.empty(self.n, dtype=self.dtype, device=self.device) if potential else None
+        _check(load_library().enuf_energy_forces(self._h, _ptr(x), _ptr(q), _ptr(E), _ptr(F), _ptr(phi)),
+               self._h)
+        self._keep = (x, q)
+        return E, F, phi
+
+    def energy_grad(self, grad_E=1.0, dx=True, dq=True):
+        """Exact gradient of the last evaluated energy, scaled by grad_E."""
+        self._bind_stream()
+        gx = torch.empty((self.n, 3), dtype=self.dtype, device=self.device) if dx else None
+        gq = torch.empty(self.n, dtype=self.dtype, device=self.device) if dq else None
+        _check(load_library().enuf_energy_grad(self._h, float(grad_E), _ptr(gx), _ptr(gq)), self._h)
+        return gx, gq
+
+    def flags(self):
+        f = ctypes.c_int32()
+        _check(load_library().enuf_get_flags(self._h, ctypes.byref(f)), self._h)
+        return int(f.value)
+
+    def stage(self, which):
+        """Copy of an internal buffer of the last evaluation (see enuf_stage)."""
+        lib = load_library()
+        nb = ctypes.c_size_t()
+        _check(lib.enuf_stage_bytes(self._h, int(which), ctypes.byref(nb)), self._h)
+        buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(lib.enuf_stage_copy(self._h, int(which), _ptr(buf), nb.value), self._h)
+        G = self.M[0] * self.M[1] * self.M[2]
+        Mx, My, Mz = self.M
+        if which == STAGE_GRID:
+            return buf.view(self.dtype).view(Mz, My, Mx)
+        if which == STAGE_SPECTRUM:
+            return buf.view(self.dtype).view(Mz, My, Mx // 2, 2)
+        if which == STAGE_FIELDS:
+            return buf.view(self.dtype).view(Mz, My, Mx, 4)
+        return buf.view(torch.int32)
+
+    def timings(self):
+        lib = load_library()
+        arr = (ctypes.c_double * len(PHASES))()
+        cnt = ctypes.c_int32()
+        _check(lib.enuf_get_timings(self._h, arr, len(PHASES), ctypes.byref(cnt)), self._h)
+        return dict(zip(PHASES, list(arr)[: cnt.value]))
+
+
+class EnufEnergy(torch.autograd.Function):
+    """E = ENUF energy of (x, q); backward gives the exact dE/dx and dE/dq of
+    the computed energy through the library's adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, x, q, engine):
+        E, _, _ = engine.energy_forces(x.detach(), q.detach(), forces=False, potential=True)
+        ctx.engine = engine
+        return E[0].clone()
+
+    @staticmethod
+    def backward(ctx, gE):
+        g = float(gE.item())
+        dx, dq = ctx.engine.energy_grad(g, dx=ctx.needs_input_grad[0], dq=ctx.needs_input_grad[1])
+        return dx, dq, None
+
+
+def enuf_energy(x, q, engine):
+    return EnufEnergy.apply(x, q, engine)
+
+
+def device_count() -> int:
+    return int(load_library().enuf_device_count())

@@ -1,0 +1,117 @@
+"""GPU adjoint: enuf_energy_grad and the EnufEnergy autograd function.
+
+The adjoint returns the exact gradient of the energy the library computed.
+It is checked against (i) the numpy mirror's exact gradient of the same
+discrete energy (FP64, rounding-level agreement), (ii) central finite
+differences of the GPU's own FP64 energy, (iii) the direct Ewald oracle's
+analytic gradient (within the method's error) and (iv) the quadratic-form
+identity sum_i q_i dE/dq_i = 2E.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import enuf_mirror as em  # noqa: E402
+from oracle import ewald as ew  # noqa: E402
+from paper_2004_12484_amd import enuf, inputs  # noqa: E402
+
+from gpu_util import rms_rel, run, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _sys(n=900, box=(10.0, 11.0, 12.0), seed=11):
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, float)
+    x = rng.uniform(0, 1, (n, 3)) * box
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * rng.uniform(0.5, 1.5, n)
+    q[::7] = 0.0
+    return x, q, box
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_matches_mirror_gradient(prec):
+    x, q, box = _sys()
+    M, p, alpha, rc = (32, 32, 32), 6, 1.1, 4.0
+    eng, out = run(x, q, box, alpha, rc, M, p, precision=prec)
+    gx, gq = eng.energy_grad(1.0)
+    m = em.enuf(x, q, box, alpha, rc, M, p)
+    tol = 1e-10 if prec == "f64" else 3e-5
+    assert rms_rel(gx.double().cpu().numpy(), m["grad_x"]) <= tol
+    assert rms_rel(gq.double().cpu().numpy(), m["phi"]) <= tol
+    # scaling by grad_E
+    gx2, gq2 = eng.energy_grad(-2.5)
+    scale = float(gx.abs().max())
+    assert float((gx2 + 2.5 * gx).abs().max()) <= (1e-5 if prec == "f32" else 1e-13) * 2.5 * scale
+
+
+def test_adjoint_is_finite_difference_of_gpu_energy():
+    x, q, box = _sys(seed=12)
+    M, p, alpha, rc = (32, 32, 32), 6, 1.1, 4.0
+    eng = enuf.Enuf(box, len(q), alpha, rc, M, p)
+    qt = to_dev(q, torch.float64)
+    xt = to_dev(x, torch.float64)
+    eng.energy_forces(xt, qt, forces=False, potential=True)
+    gx, gq = eng.energy_grad(1.0)
+    gx = gx.cpu().numpy()
+    gq = gq.cpu().numpy()
+    h = 1e-5
+
+    def energy(xa, qa):
+        E, _, _ = eng.energy_forces(to_dev(xa, torch.float64), to_dev(qa, torch.float64), forces=False)
+        return float(E[0].item())
+
+    # sample particles away from the cutoff sphere edge (erfc(a r_c)/r_c jumps there)
+    for i in (3, 100, 501):
+        d = x[i] - x
+        d -= box * np.round(d / box)
+        r = np.linalg.norm(d, axis=1)
+        if np.any(np.abs(r[q != 0] - rc) < 1e-3):
+            continue
+        for dd in range(3):
+            xp = x.copy(); xp[i, dd] += h
+            xm = x.copy(); xm[i, dd] -= h
+            fd = (energy(xp, q) - energy(xm, q)) / (2 * h)
+            assert abs(fd - gx[i, dd]) <= 1e-6 * max(1.0, np.abs(gx).max())
+        qp = q.copy(); qp[i] += h
+        qm = q.copy(); qm[i] -= h
+        fd = (energy(x, qp) - energy(x, qm)) / (2 * h)
+        assert abs(fd - gq[i]) <= 1e-6 * max(1.0, np.abs(gq).max())
+
+
+def test_quadratic_form_identity_on_gpu():
+    x, q, box = _sys(seed=13)
+    eng, out = run(x, q, box, 1.1, 4.0, (32, 32, 32), 6)
+    _, gq = eng.energy_grad(1.0)
+    s = float(np.dot(q, gq.cpu().numpy()))
+    assert abs(s - 2 * out["E"][0]) <= 1e-11 * (abs(out["E"][1]) + abs(out["E"][2]) + abs(out["E"][3]))
+
+
+def test_adjoint_vs_oracle_analytic_gradient():
+    w = inputs.nacl()
+    eng, out = run(w.x, w.q, w.box, w.alpha, w.r_c, w.M, w.p)
+    gx, gq = eng.energy_grad(1.0)
+    ref = ew.ewald(w.x, w.q, w.box, w.alpha, w.r_c)
+    assert rms_rel(-gx.cpu().numpy(), ref["F"]) <= 1e-4
+    assert rms_rel(gq.cpu().numpy(), ref["phi"]) <= 1e-5
+
+
+def test_autograd_function():
+    x, q, box = _sys(seed=14)
+    eng = enuf.Enuf(box, len(q), 1.1, 4.0, (32, 32, 32), 6)
+    xt = to_dev(x, torch.float64).requires_grad_(True)
+    qt = to_dev(q, torch.float64).requires_grad_(True)
+    E = enuf.enuf_energy(xt, qt, eng)
+    (3.0 * E).backward()
+    m = em.enuf(x, q, box, 1.1, 4.0, (32, 32, 32), 6)
+    assert abs(E.item() - m["E"]) <= 1e-11 * abs(m["E_K"])
+    assert rms_rel(xt.grad.cpu().numpy(), 3.0 * m["grad_x"]) <= 1e-10
+    assert rms_rel(qt.grad.cpu().numpy(), 3.0 * m["phi"]) <= 1e-10
+
+
+def test_grad_before_forward_is_state_error():
+    eng = enuf.Enuf((8.0, 8.0, 8.0), 10, 1.0, 3.0, (16, 16, 16), 4)
+    with pytest.raises(enuf.EnufError) as ei:
+        eng.energy_grad(1.0)
+    assert ei.value.status == enuf.ENUF_ESTATE
