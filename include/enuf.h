@@ -64,7 +64,9 @@ typedef enum { ENUF_FP64 = 0, ENUF_FP32 = 1 } enuf_precision;
 /* Options for enuf_set_option(). */
 typedef enum {
     ENUF_OPT_KE = 0,          /* Coulomb prefactor 1/(4 pi eps0 eps_r); default 1 */
-    ENUF_OPT_TIMING = 1,      /* 1: record per-phase HIP event times; default 0 */
+    ENUF_OPT_TIMING = 1,      /* n > 0: record per-phase HIP events for each
+                                    evaluation in a ring of n slots; 0: off
+                                    (default) */
     ENUF_OPT_GRAPH = 2,       /* 1: replay the launch sequence as a HIP graph; default 0 */
     ENUF_OPT_CHECK = 3        /* 1: enuf_energy_forces synchronises and reports
                                     ENUF_ENONFINITE itself; default 0 */
@@ -77,7 +79,8 @@ typedef enum {
                                  [Mz][My][Mx/2], the z transform not applied
                                  (it happens fused with the influence step) */
     ENUF_STAGE_FIELDS = 2,    /* real-space fields after the inverse FFTs, real
-                                 [Mz][My][Mx][4] = (E_x, E_y, E_z, psi) */
+                                 [Mz][My][Mx][4] = (E_x, E_y, E_z, psi); psi is
+                                 0 unless the evaluation requested phi */
     ENUF_STAGE_SORTED = 3,    /* int32 [N] permutation, grid-tile order
                                  (entries past the active count are unused) */
     ENUF_STAGE_COUNTS = 4,    /* int32 [2]: active particles, charged particles */
@@ -123,7 +126,9 @@ enuf_status enuf_set_stream(enuf_ctx ctx, void *stream);
  *   E    device double[5] out: (total, E_R, E_K, E_self, E_bg)
  *   F    device real[N*3] out forces, or NULL for energy only
  *   phi  device real[N] out potentials phi_i = dE/dq_i, or NULL.  When
- *        given, every particle (neutral ones too) gets its potential.
+ *        given, every particle (neutral ones too) gets its potential and the
+ *        potential field is transformed as a fourth inverse FFT; without it
+ *        only the three force fields are.
  * The reciprocal forces are the ik-differentiated ones of Eq. 41-42, which
  * sum to zero exactly; they approximate -dE/dr.  The exact gradient of the
  * computed energy is available from enuf_energy_grad().  Non-finite input is
@@ -137,7 +142,9 @@ enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, doubl
  * enuf_energy_grad -- adjoint of the last enuf_energy_forces() on this
  * context: the exact gradient of the energy E it computed, scaled by
  * grad_E.  Uses the sorted particles and the potential grid kept from that
- * call (x and q are not read again).
+ * call (x and q are not read again); that call must have requested phi
+ * (which makes every particle active and transforms the potential field),
+ * otherwise ENUF_ESTATE.
  *   dEdx  device real[N*3] out: grad_E * dE/dr_i (window-derivative gather on
  *         the potential grid, plus the real-space gradient), or NULL
  *   dEdq  device real[N] out: grad_E * dE/dq_i, or NULL
@@ -156,10 +163,13 @@ enuf_status enuf_stage_copy(enuf_ctx ctx, int32_t stage, void *dst, size_t bytes
 /* enuf_stage_bytes -- size in bytes of an enuf_stage buffer. */
 enuf_status enuf_stage_bytes(enuf_ctx ctx, int32_t stage, size_t *bytes);
 
-/* enuf_get_timings -- per-phase milliseconds of the last evaluation when
- * ENUF_OPT_TIMING is on (synchronises).  Fills up to n values in the order
- * prep, sort, spread, fft_fwd, influence+z, fft_inv, gather, pair, finalize;
- * *count receives the number of phases. */
+/* enuf_get_timings -- per-phase milliseconds averaged over the evaluations
+ * recorded since the previous read (at most the ring size set with
+ * ENUF_OPT_TIMING), measured with HIP events on the context's stream;
+ * synchronises, then starts a new averaging window.  Fills up to n values in
+ * the order prep, sort, spread, fft_fwd, influence+z, fft_inv, gather, pair,
+ * finalize; *count receives the number of phases.  ENUF_ESTATE when timing
+ * is off or nothing was recorded. */
 enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count);
 
 /* enuf_status_string -- static text for a status code. */

@@ -24,10 +24,10 @@ struct enuf_ctx_s {
   int device = 0;
   bool have_forward = false;
   bool last_all_active = false;
-  bool timing = false;
   bool check = false;
-  hipEvent_t ev[enuf::kPhases + 1] = {};
-  bool ev_ok = false;
+  // timing ring: `slots` evaluations x (kPhases + 1) events
+  std::vector<hipEvent_t> ring;
+  int slots = 0, next = 0, recorded = 0;
   std::string err;
   std::vector<void *> allocs;
 };
@@ -49,9 +49,9 @@ static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 static void free_all(enuf_ctx c) {
   for (void *p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
-  if (c->ev_ok)
-    for (auto &e : c->ev) (void)hipEventDestroy(e);
-  c->ev_ok = false;
+  for (auto &e : c->ring) (void)hipEventDestroy(e);
+  c->ring.clear();
+  c->slots = c->next = c->recorded = 0;
 }
 
 template <typename T>
@@ -154,7 +154,10 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   ok = ok && need(dalloc(c, &w.rank_t, (size_t)n));
   ok = ok && need(dalloc(c, &w.key_c, (size_t)n));
   ok = ok && need(dalloc(c, &w.rank_c, (size_t)n));
-  ok = ok && need(dalloc(c, &w.off_t, (size_t)2 * g.ntiles + 1));
+  ok = ok && need(dalloc(c, &w.off_t, (size_t)enuf::kTileBins * g.ntiles + 1));
+  ok = ok && need(dalloc(c, &w.bsum, (size_t)enuf::nblk_scan(g)));
+  ok = ok && need(dalloc(c, &w.bev, (size_t)enuf::nblk_scan(g)));
+  ok = ok && need(dalloc(c, &w.runs, (size_t)5 * enuf::kMaxRuns));
   ok = ok && need(dalloc(c, &w.off_c, (size_t)2 * g.ncells + 1));
   ok = ok && need(dalloc(c, &w.counts, 4));
   ok = ok && need(dalloc(c, &w.scal, 4));
@@ -177,7 +180,15 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   std::vector<unsigned char> host(ntab * rs);
   if (precision == ENUF_FP64) enuf::fill_tables<double>(g, w.tab_off, (double *)host.data());
   else enuf::fill_tables<float>(g, w.tab_off, (float *)host.data());
+  int runs[5 * enuf::kMaxRuns];
+  w.nruns = enuf::build_runs(g, runs);
+  if (w.nruns <= 0) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, ENUF_EUNSUPPORTED, "spread run table overflow");
+  }
   e = hipMemcpy(w.tables, host.data(), ntab * rs, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(w.runs, runs, sizeof(int) * 5 * w.nruns, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(w.counts, 0, 4 * sizeof(int));
   if (e == hipSuccess) e = hipMemset(w.kpart, 0, sizeof(double));
   if (e != hipSuccess) {
@@ -207,17 +218,26 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       if (!(value > 0.0) || !std::isfinite(value)) return fail(ctx, ENUF_EINVAL, "ke must be > 0");
       ctx->g.ke = value;
       return ENUF_OK;
-    case ENUF_OPT_TIMING:
-      if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "timing is 0 or 1");
-      if (value == 1.0 && !ctx->ev_ok) {
-        for (auto &e : ctx->ev) {
+    case ENUF_OPT_TIMING: {
+      if (!(value >= 0.0 && value <= 4096.0) || value != std::floor(value))
+        return fail(ctx, ENUF_EINVAL, "timing slots must be an integer in [0, 4096]");
+      for (auto &e : ctx->ring) (void)hipEventDestroy(e);
+      ctx->ring.clear();
+      ctx->slots = ctx->next = ctx->recorded = 0;
+      const int slots = (int)value;
+      if (slots > 0) {
+        ctx->ring.resize((size_t)slots * (enuf::kPhases + 1));
+        for (auto &e : ctx->ring) {
           hipError_t r = hipEventCreate(&e);
-          if (r != hipSuccess) return hip_fail(ctx, r, "hipEventCreate");
+          if (r != hipSuccess) {
+            e = nullptr;
+            return hip_fail(ctx, r, "hipEventCreate");
+          }
         }
-        ctx->ev_ok = true;
+        ctx->slots = slots;
       }
-      ctx->timing = value == 1.0;
       return ENUF_OK;
+    }
     case ENUF_OPT_GRAPH:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "graph is 0 or 1");
       if (value == 1.0) return fail(ctx, ENUF_EUNSUPPORTED, "graph replay is not available in this build");
@@ -256,13 +276,18 @@ enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, doubl
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   const bool all = phi != nullptr;
-  hipEvent_t *ev = ctx->timing ? ctx->ev : nullptr;
+  hipEvent_t *ev = nullptr;
+  if (ctx->slots > 0) {
+    ev = &ctx->ring[(size_t)ctx->next * (enuf::kPhases + 1)];
+    ctx->next = (ctx->next + 1) % ctx->slots;
+    ctx->recorded = std::min(ctx->recorded + 1, ctx->slots);
+  }
   if (ctx->prec == ENUF_FP64)
     e = enuf::launch_forward<double>(ctx->g, ctx->w, ctx->st, (const double *)x, (const double *)q, E,
-                                     (double *)F, (double *)phi, all, ev);
+                                     (double *)F, (double *)phi, all, all, ev);
   else
     e = enuf::launch_forward<float>(ctx->g, ctx->w, ctx->st, (const float *)x, (const float *)q, E,
-                                    (float *)F, (float *)phi, all, ev);
+                                    (float *)F, (float *)phi, all, all, ev);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->have_forward = true;
   ctx->last_all_active = all;
@@ -279,8 +304,8 @@ enuf_status enuf_energy_grad(enuf_ctx ctx, double grad_E, void *dEdx, void *dEdq
   if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
   if (!std::isfinite(grad_E)) return fail(ctx, ENUF_EINVAL, "grad_E must be finite");
   if (!ctx->have_forward) return fail(ctx, ENUF_ESTATE, "no forward evaluation on this context");
-  if (dEdq && !ctx->last_all_active)
-    return fail(ctx, ENUF_ESTATE, "dE/dq needs the forward call made with phi != NULL");
+  if (!ctx->last_all_active)
+    return fail(ctx, ENUF_ESTATE, "the adjoint needs the forward call made with phi != NULL");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (ctx->prec == ENUF_FP64)
@@ -335,16 +360,23 @@ enuf_status enuf_stage_copy(enuf_ctx ctx, int32_t stage, void *dst, size_t bytes
 
 enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count) {
   if (!ctx || !ms || !count) return fail(ctx, ENUF_EINVAL, "NULL argument");
-  if (!ctx->timing || !ctx->have_forward) return fail(ctx, ENUF_ESTATE, "timing is off or nothing ran");
-  hipError_t e = hipEventSynchronize(ctx->ev[enuf::kPhases]);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
-  *count = enuf::kPhases;
-  for (int i = 0; i < enuf::kPhases && i < n; ++i) {
-    float t = 0.f;
-    e = hipEventElapsedTime(&t, ctx->ev[i], ctx->ev[i + 1]);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
-    ms[i] = t;
+  if (ctx->slots == 0 || ctx->recorded == 0) return fail(ctx, ENUF_ESTATE, "timing is off or nothing ran");
+  hipError_t e = ctx->st ? hipStreamSynchronize(ctx->st) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(ctx, e, "synchronize");
+  double acc[enuf::kPhases] = {0};
+  for (int k = 0; k < ctx->recorded; ++k) {
+    const int slot = (ctx->next - 1 - k + 2 * ctx->slots) % ctx->slots;
+    hipEvent_t *ev = &ctx->ring[(size_t)slot * (enuf::kPhases + 1)];
+    for (int i = 0; i < enuf::kPhases; ++i) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+      acc[i] += t;
+    }
   }
+  *count = enuf::kPhases;
+  for (int i = 0; i < enuf::kPhases && i < n; ++i) ms[i] = acc[i] / ctx->recorded;
+  ctx->recorded = 0;
   return ENUF_OK;
 }
 

@@ -15,6 +15,13 @@ constexpr int kTileX = 16;           // spread tile (grid points) before clampin
 constexpr int kTileY = 8;
 constexpr int kTileZ = 8;
 constexpr int kMaxTilePts = kTileX * kTileY * kTileZ;
+constexpr int kClasses = 27;         // stencil spill classes per tile (3 digits: low/none/high)
+constexpr int kTileBins = 2 * kClasses;  // sort bins per tile: charged classes, then neutral
+constexpr int kMaxRuns = 256;        // neighbour (tile, class-range) runs read by one spread tile
+constexpr int kPairBlock = 256;      // threads per cell in the pair kernel
+constexpr int kPairChunk = 512;      // neighbour particles staged in LDS at a time
+constexpr int kScanBlock = 256;      // threads per scan block
+constexpr int kScanChunk = 4 * kScanBlock;  // bins per scan block
 
 // Geometry and parameters, passed by value to kernels.
 struct Geom {
@@ -40,13 +47,17 @@ struct Work {
   int *rank_t = nullptr;    // [n]
   int *key_c = nullptr;     // [n]
   int *rank_c = nullptr;    // [n]
-  int *off_t = nullptr;     // [2*ntiles + 1] counts, then exclusive offsets
+  int *off_t = nullptr;     // [kTileBins*ntiles + 1] counts, then exclusive offsets
   int *off_c = nullptr;     // [2*ncells + 1]
+  int *bsum = nullptr;      // [scan blocks] block totals, then block prefixes
+  int *bev = nullptr;       // [scan blocks] charged subtotals
+  int *runs = nullptr;      // [5*nruns] spread neighbour runs (dx, dy, dz, class lo, class hi)
+  int nruns = 0;
   int *counts = nullptr;    // [4]: active, charged, flags, spare
   double *scal = nullptr;   // [4]: Q, Q2, spare
   double *qpart = nullptr;  // [2*nblk_prep] partial sums of q, q^2
   double *kpart = nullptr;  // [nblk_z] partial reciprocal energies
-  double *rpart = nullptr;  // [nblk_pair] partial real-space energies
+  double *rpart = nullptr;  // [ncells] partial real-space energies
   void *grid = nullptr;     // real [G]
   void *spec = nullptr;     // complex [G/2]
   void *fspec = nullptr;    // complex [4][G/2]
@@ -58,6 +69,10 @@ struct Work {
 // Launch-configuration numbers the host needs to size partial buffers.
 int nblk_prep(const Geom &g);
 int nblk_pair(const Geom &g);
+int nblk_scan(const Geom &g);
+// Runs of (neighbour tile offset, class range) a spread tile reads; returns
+// the number of runs and writes 5 ints per run into out (kMaxRuns capacity).
+int build_runs(const Geom &g, int *out);
 int nblk_z(const Geom &g, bool fp64);
 
 // Fill the twiddle / window tables on the host (size in reals returned by
@@ -70,7 +85,7 @@ template <typename R> void fill_tables(const Geom &g, const size_t off[8], R *ho
 constexpr int kPhases = 9;
 template <typename R>
 hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R *x, const R *q,
-                          double *E, R *F, R *phi, bool all_active, hipEvent_t *ev);
+                          double *E, R *F, R *phi, bool all_active, bool want_psi, hipEvent_t *ev);
 
 // Adjoint of the last forward: dEdx, dEdq (either may be null).
 template <typename R>

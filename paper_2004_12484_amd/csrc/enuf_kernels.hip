@@ -171,7 +171,19 @@ __global__ void k_fill_real(R *p, long long n) {
 
 // --------------------------------------------------------------------------
 // prep: wrap, keys, counting-sort ranks, charge sums
+//
+// Reciprocal-path key: (tile, charged/neutral, spill class).  Along each axis
+// a particle's stencil either stays inside its tile (digit 1), crosses the low
+// face (digit 0) or the high face (digit 2); the class is the three digits.
+// With that order a tile can read, from each neighbouring tile, exactly the
+// particles whose stencils reach it, as a few contiguous runs.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ int spill_digit(int local, int T, int P) {
+  if (local < P / 2 - 1) return 0;
+  if (local > T - 1 - P / 2) return 2;
+  return 1;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const R *__restrict__ q, Geom g,
                                                  int all_active, int *__restrict__ key_t,
@@ -191,17 +203,20 @@ __global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const 
     }
     if (active) {
       const R p3[3] = {px, py, pz};
-      int tix[3], cix[3];
+      int tix[3], cix[3], dig[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const R xw = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
         const R sg = grid_coord(xw, R(g.M[d] / g.L[d]), g.M[d]);
-        tix[d] = (int)sg / g.T[d];
+        const int gi = (int)sg;
+        tix[d] = gi / g.T[d];
+        dig[d] = spill_digit(gi - tix[d] * g.T[d], g.T[d], g.p);
         const int ci = (int)(xw * R(g.nc[d] / g.L[d]));
         cix[d] = ci < g.nc[d] ? ci : g.nc[d] - 1;
       }
       const int neutral = (qi == R(0)) ? 1 : 0;
-      const int kt = 2 * ((tix[2] * g.nt[1] + tix[1]) * g.nt[0] + tix[0]) + neutral;
+      const int tile = (tix[2] * g.nt[1] + tix[1]) * g.nt[0] + tix[0];
+      const int kt = tile * kTileBins + neutral * kClasses + (dig[0] * 9 + dig[1] * 3 + dig[2]);
       const int kc = 2 * ((cix[2] * g.nc[1] + cix[1]) * g.nc[0] + cix[0]) + neutral;
       key_t[i] = kt;
       key_c[i] = kc;
@@ -222,69 +237,116 @@ __global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const 
   }
 }
 
-// Exclusive scan of cnt[0..len) in place, cnt[len] = total, by one block of
-// 1024 threads; returns (in *even_sum) the sum of the even-index counts.
-__device__ void block_exscan(int *cnt, int len, int *even_sum) {
-  __shared__ int part[1024];
-  __shared__ int evs[1024];
-  const int nt = blockDim.x, t = threadIdx.x;
-  const int chunk = (len + nt - 1) / nt;
-  const int lo = min(len, t * chunk), hi = min(len, lo + chunk);
-  int s = 0, ev = 0;
-  for (int i = lo; i < hi; ++i) {
-    s += cnt[i];
-    if ((i & 1) == 0) ev += cnt[i];
+// Exclusive scans of the two bin arrays, in three launches:
+//  scan1: each block scans kScanChunk bins in place (within-block prefix) and
+//         writes its total (and, for the tile bins, its charged subtotal)
+//  scan2: one block scans the block totals of each array, writes the grand
+//         totals, the active/charged counts and the charge sums
+//  scan3: each block adds its block prefix to its bins
+__device__ int block_exscan_int(int v, int *total) {
+  __shared__ int wsum[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
   }
-  part[t] = s;
-  evs[t] = ev;
+  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
-  // Hillis-Steele inclusive scan of part[]
-  for (int o = 1; o < nt; o <<= 1) {
-    int v = (t >= o) ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  int before = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int t = wsum[k];
+    if (k < wv) before += t;
+    tot += t;
   }
-  int run = part[t] - s;
-  for (int i = lo; i < hi; ++i) {
-    const int c = cnt[i];
-    cnt[i] = run;
-    run += c;
-  }
-  if (t == nt - 1) cnt[len] = part[nt - 1];
   __syncthreads();
-  if (t == 0) {
-    int e = 0;
-    for (int i = 0; i < nt; ++i) e += evs[i];
-    *even_sum = e;
+  *total = tot;
+  return before + inc - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan1(int *off_t, int nbt, int *off_c, int nbc, int bt,
+                                                      int *bsum, int *bev) {
+  const int b = blockIdx.x;
+  const bool tiles = b < bt;
+  int *arr = tiles ? off_t : off_c;
+  const int len = tiles ? nbt : nbc;
+  const int base = (tiles ? b : b - bt) * kScanChunk;
+  const int i0 = base + threadIdx.x * 4;
+  int v[4], s = 0, ev = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (i0 + k < len) ? arr[i0 + k] : 0;
+    s += v[k];
+    if (tiles && ((i0 + k) % kTileBins) < kClasses) ev += v[k];
+  }
+  int tot;
+  int run = block_exscan_int(s, &tot);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < len) arr[i0 + k] = run;
+    run += v[k];
+  }
+  int evt;
+  (void)block_exscan_int(ev, &evt);
+  if (threadIdx.x == 0) {
+    bsum[b] = tot;
+    bev[b] = evt;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_scan(int *off_t, int len_t, int *off_c, int len_c,
-                                               const double *qpart, int nqp, double *scal,
-                                               int *counts) {
-  __shared__ int ev;
-  if (blockIdx.x == 0) {
-    block_exscan(off_t, len_t, &ev);
+__global__ __launch_bounds__(1024) void k_scan2(int *bsum, const int *bev, int bt, int bc, int *off_t, int nbt,
+                                                int *off_c, int nbc, const double *qpart, int nqp, double *scal,
+                                                int *counts) {
+  __shared__ int carry;
+  for (int seg = 0; seg < 2; ++seg) {
+    const int lo = seg == 0 ? 0 : bt, n = seg == 0 ? bt : bc;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+      const int i = c0 + threadIdx.x;
+      const int v = i < n ? bsum[lo + i] : 0;
+      int tot;
+      const int ex = block_exscan_int(v, &tot);
+      const int cy = carry;
+      if (i < n) bsum[lo + i] = cy + ex;
+      __syncthreads();
+      if (threadIdx.x == 0) carry = cy + tot;
+      __syncthreads();
+    }
     if (threadIdx.x == 0) {
-      counts[0] = off_t[len_t];
-      counts[1] = ev;
+      if (seg == 0) { off_t[nbt] = carry; counts[0] = carry; }
+      else off_c[nbc] = carry;
     }
-  } else if (blockIdx.x == 1) {
-    block_exscan(off_c, len_c, &ev);
-  } else {
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nqp; i += blockDim.x) {
-      a += qpart[2 * i];
-      b += qpart[2 * i + 1];
-    }
-    a = block_sum(a);
-    b = block_sum(b);
-    if (threadIdx.x == 0) {
-      scal[0] = a;
-      scal[1] = b;
-    }
+    __syncthreads();
   }
+  int ev = 0;
+  for (int i = threadIdx.x; i < bt; i += blockDim.x) ev += bev[i];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nqp; i += blockDim.x) {
+    a += qpart[2 * i];
+    b += qpart[2 * i + 1];
+  }
+  const double evd = block_sum((double)ev);
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) {
+    counts[1] = (int)evd;
+    scal[0] = a;
+    scal[1] = b;
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan3(int *off_t, int nbt, int *off_c, int nbc, int bt,
+                                                      const int *bsum) {
+  const int b = blockIdx.x;
+  const bool tiles = b < bt;
+  int *arr = tiles ? off_t : off_c;
+  const int len = tiles ? nbt : nbc;
+  const int base = (tiles ? b : b - bt) * kScanChunk;
+  const int add = bsum[b];
+  for (int k = threadIdx.x; k < kScanChunk; k += blockDim.x)
+    if (base + k < len) arr[base + k] += add;
 }
 
 template <typename R>
@@ -327,22 +389,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const R *__restrict__ x, con
 // spread: rho_l = sum_i q_i B(s_i - l)   (type-1 gridding, Eq. 36)
 //
 // One workgroup owns one grid tile of T_x*T_y*T_z points and accumulates it in
-// LDS; it pulls every charged particle whose stencil reaches the tile from the
-// (up to) 27 neighbouring tiles' sorted ranges, so each grid point is written
-// exactly once, with no global atomics.  Staging: threads compute, for a batch
-// of candidates, the box of stencil points inside the tile and the 3*P window
-// weights (charge folded into z) into LDS; then each wavefront takes one staged
-// particle at a time and its 64 lanes sweep that particle's box.
+// LDS, so each grid point is written exactly once and no global atomics are
+// used.  It pulls exactly the charged particles whose stencils reach the tile:
+// its own, plus, from each neighbouring tile, the spill classes facing it (a
+// host-built table of runs: neighbour offset and class range).  Staging:
+// threads compute, for a batch of particles, the box of stencil points inside
+// the tile and the 3*P window weights (charge folded into z) into LDS; then
+// each wavefront takes one staged particle at a time and its 64 lanes sweep
+// that particle's box with LDS atomic adds.
 // --------------------------------------------------------------------------
+template <typename R>
+constexpr int spread_block() { return sizeof(R) == 8 ? 128 : 256; }
+
 template <typename R, int P>
-__global__ __launch_bounds__(kBlock) void k_spread(const real4<R> *__restrict__ part,
-                                                   const int *__restrict__ off_t, Geom g,
+__global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__restrict__ part,
+                                                   const int *__restrict__ off_t,
+                                                   const int *__restrict__ runs, int nruns, Geom g,
                                                    R *__restrict__ grid) {
-  __shared__ R acc[kMaxTilePts];
-  __shared__ R wst[kBlock][3][P];
-  __shared__ int box[kBlock][3];  // per axis: lstart | count << 8 | jstart << 16
-  __shared__ int rstart[27], rpre[28];
-  __shared__ int nrange, nstaged;
+  // one private accumulator per wavefront: a wave only ever adds one
+  // particle's (distinct) box points per instruction, so plain LDS
+  // read-modify-write is race free and avoids the slow LDS float atomics
+  constexpr int NB = spread_block<R>();
+  __shared__ R acc[NB / 64][kMaxTilePts];
+  __shared__ R wst[NB][3][P];
+  __shared__ int box[NB][3];  // per axis: lstart | count << 8 | jstart << 16
+  __shared__ int rstart[kMaxRuns], rpre[kMaxRuns + 1];
+  __shared__ int nstaged;
 
   const int tid = threadIdx.x;
   int t = blockIdx.x;
@@ -352,35 +424,41 @@ __global__ __launch_bounds__(kBlock) void k_spread(const real4<R> *__restrict__ 
   const int tz = t / g.nt[1];
   const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
   const int tpts = g.T[0] * g.T[1] * g.T[2];
-  for (int e = tid; e < tpts; e += blockDim.x) acc[e] = R(0);
+  for (int e = tid; e < tpts; e += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < NB / 64; ++k) acc[k][e] = R(0);
 
-  if (tid == 0) {
-    // neighbouring tiles (distinct ones only), charged sub-ranges
-    int offs[3][3], no[3];
-    const int tc[3] = {tx, ty, tz};
-    for (int d = 0; d < 3; ++d) {
-      if (g.nt[d] >= 3) { offs[d][0] = -1; offs[d][1] = 0; offs[d][2] = 1; no[d] = 3; }
-      else { offs[d][0] = 0; offs[d][1] = 1; no[d] = 2; }
-    }
-    int nr = 0, run = 0;
-    for (int a = 0; a < no[2]; ++a)
-      for (int b = 0; b < no[1]; ++b)
-        for (int c = 0; c < no[0]; ++c) {
-          const int nz = (tc[2] + offs[2][a] + g.nt[2]) % g.nt[2];
-          const int ny = (tc[1] + offs[1][b] + g.nt[1]) % g.nt[1];
-          const int nx = (tc[0] + offs[0][c] + g.nt[0]) % g.nt[0];
-          const int tt = (nz * g.nt[1] + ny) * g.nt[0] + nx;
-          const int s = off_t[2 * tt], e = off_t[2 * tt + 1];
-          rstart[nr] = s;
-          rpre[nr] = run;
-          run += e - s;
-          ++nr;
-        }
-    rpre[nr] = run;
-    nrange = nr;
+  // runs -> particle ranges, then an exclusive prefix over their lengths
+  for (int k = tid; k < nruns; k += blockDim.x) {
+    const int *rr = runs + 5 * k;
+    const int nx = (tx + rr[0] + g.nt[0]) % g.nt[0];
+    const int ny = (ty + rr[1] + g.nt[1]) % g.nt[1];
+    const int nz = (tz + rr[2] + g.nt[2]) % g.nt[2];
+    const int tt = (nz * g.nt[1] + ny) * g.nt[0] + nx;
+    const int s0 = off_t[tt * kTileBins + rr[3]];
+    const int s1 = off_t[tt * kTileBins + rr[4] + 1];
+    rstart[k] = s0;
+    rpre[k + 1] = s1 - s0;
   }
   __syncthreads();
-  const int total = rpre[nrange];
+  if (tid < 64) {
+    int carry = 0;
+    for (int c0 = 0; c0 < nruns; c0 += 64) {
+      const int k = c0 + tid;
+      const int v = k < nruns ? rpre[k + 1] : 0;
+      int inc = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (tid >= o) inc += u;
+      }
+      if (k < nruns) rpre[k + 1] = carry + inc;
+      carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) rpre[0] = 0;
+  }
+  __syncthreads();
+  const int total = rpre[nruns];
   const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
 
   for (int base = 0; base < total; base += blockDim.x) {
@@ -388,9 +466,13 @@ __global__ __launch_bounds__(kBlock) void k_spread(const real4<R> *__restrict__ 
     __syncthreads();
     const int c = base + tid;
     if (c < total) {
-      int r = 0;
-      while (rpre[r + 1] <= c) ++r;
-      const real4<R> v = part[rstart[r] + (c - rpre[r])];
+      // range holding candidate c (binary search over the run prefix)
+      int lo = 0, hi = nruns;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rpre[mid] <= c) lo = mid; else hi = mid;
+      }
+      const real4<R> v = part[rstart[lo] + (c - rpre[lo])];
       const R s[3] = {v.x, v.y, v.z};
       int ls[3], cnt[3], js[3];
       R fr[3];
@@ -427,20 +509,23 @@ __global__ __launch_bounds__(kBlock) void k_spread(const real4<R> *__restrict__ 
     }
     __syncthreads();
     const int ns = nstaged;
+    R *my = acc[wv];
     for (int sp = wv; sp < ns; sp += nwv) {
       const int bx = box[sp][0], by = box[sp][1], bz = box[sp][2];
       const int lx = bx & 255, cx = (bx >> 8) & 255, jx = bx >> 16;
       const int ly = by & 255, cy = (by >> 8) & 255, jy = by >> 16;
       const int lz = bz & 255, cz = (bz >> 8) & 255, jz = bz >> 16;
       const int cyx = cy * cx, npts = cz * cyx;
-      const float inv_yx = 1.0f / (float)cyx, inv_x = 1.0f / (float)cx;
+      const float inv_yx = __builtin_amdgcn_rcpf((float)cyx), inv_x = __builtin_amdgcn_rcpf((float)cx);
+      const R *wz = wst[sp][2] + jz, *wy = wst[sp][1] + jy, *wx = wst[sp][0] + jx;
+      R *row0 = my + (lz * g.T[1] + ly) * g.T[0] + lx;
       for (int pt = lane; pt < npts; pt += 64) {
         const int iz = (int)(((float)pt + 0.5f) * inv_yx);
         const int rem = pt - iz * cyx;
         const int iy = (int)(((float)rem + 0.5f) * inv_x);
         const int ix = rem - iy * cx;
-        const R val = wst[sp][2][jz + iz] * wst[sp][1][jy + iy] * wst[sp][0][jx + ix];
-        atomicAdd(&acc[((lz + iz) * g.T[1] + (ly + iy)) * g.T[0] + (lx + ix)], val);
+        R *a = row0 + (iz * g.T[1] + iy) * g.T[0] + ix;
+        *a += wz[iz] * wy[iy] * wx[ix];
       }
     }
     __syncthreads();
@@ -451,7 +536,10 @@ __global__ __launch_bounds__(kBlock) void k_spread(const real4<R> *__restrict__ 
     const int r = e / g.T[0];
     const int iy = r % g.T[1];
     const int iz = r / g.T[1];
-    grid[((size_t)(t0[2] + iz) * g.M[1] + (t0[1] + iy)) * g.M[0] + t0[0] + ix] = acc[e];
+    R v = R(0);
+#pragma unroll
+    for (int k = 0; k < NB / 64; ++k) v += acc[k][e];
+    grid[((size_t)(t0[2] + iz) * g.M[1] + (t0[1] + iy)) * g.M[0] + t0[0] + ix] = v;
   }
 }
 
@@ -575,7 +663,8 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec,
                                                     Geom g, const Cx<R> *__restrict__ tw_z,
                                                     const R *__restrict__ cwx, const R *__restrict__ cwy,
-                                                    const R *__restrict__ cwz, double *kpart, int nb) {
+                                                    const R *__restrict__ cwz, double *kpart, int nb,
+                                                    int nfield) {
   extern __shared__ unsigned char smem_raw[];
   const int n = g.M[2];
   const int hx = g.M[0] / 2;
@@ -617,7 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
     en += (kx > 0 ? 2.0 : 1.0) * (double)gv * ((double)r.x * r.x + (double)r.y * r.y);
   }
   __syncthreads();
-  for (int o = 0; o < 4; ++o) {
+  for (int o = 0; o < nfield; ++o) {
     for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
       const int f = e % nb, kz = e / nb;
       const Cx<R> r = S[e];
@@ -659,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__ fspec, real4<R> *__restrict__ field,
                                                        Geom g, const Cx<R> *__restrict__ tw_n,
-                                                       const Cx<R> *__restrict__ tw_2n, int nb) {
+                                                       const Cx<R> *__restrict__ tw_2n, int nb, int nfield) {
   extern __shared__ unsigned char smem_raw[];
   const int n = g.M[0] / 2, Mx = g.M[0];
   const size_t half = (size_t)n * g.M[1] * g.M[2];
@@ -667,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__
   Cx<R> *B = A + n * nb;
   R *out = reinterpret_cast<R *>(B + n * nb);  // [nb][Mx][4]
   const size_t row0 = (size_t)blockIdx.x * nb;
-  for (int o = 0; o < 4; ++o) {
+  for (int o = 0; o < nfield; ++o) {
     const Cx<R> *src = fspec + o * half + row0 * n;
     for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
       const int f = e / n, k = e % n;
@@ -699,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__
     v.x = out[4 * e];
     v.y = out[4 * e + 1];
     v.z = out[4 * e + 2];
-    v.w = out[4 * e + 3];
+    v.w = nfield == 4 ? out[4 * e + 3] : R(0);
     dst[e] = v;
   }
 }
@@ -803,107 +892,284 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
   }
 }
 
+// Tile form of the gather: one workgroup per grid tile stages the tile's
+// fields plus the (P-1)-point halo in LDS with coalesced row loads, then
+// interpolates every active particle of the tile from LDS.  Used when the
+// staged tile fits the LDS budget; same outputs as k_gather.
+template <typename R, int P, bool GRAD>
+__global__ __launch_bounds__(kGatherBlock) void k_gather_tile(const real4<R> *__restrict__ part,
+                                                              const int *__restrict__ perm,
+                                                              const int *__restrict__ off_t, Geom g,
+                                                              const real4<R> *__restrict__ field, R pref,
+                                                              R gscale, R *__restrict__ vec_out,
+                                                              R *__restrict__ sca_out) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ R wsh[kGatherBlock][GRAD ? 4 : 2][P];
+  real4<R> *ext = reinterpret_cast<real4<R> *>(smem_raw);
+  const int tid = threadIdx.x;
+  int t = blockIdx.x;
+  const int tx = t % g.nt[0];
+  t /= g.nt[0];
+  const int ty = t % g.nt[1];
+  const int tz = t / g.nt[1];
+  const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
+  const int E0 = g.T[0] + P - 1, E1 = g.T[1] + P - 1, E2 = g.T[2] + P - 1;
+  const int e0x = t0[0] - P / 2 + 1, e0y = t0[1] - P / 2 + 1, e0z = t0[2] - P / 2 + 1;
+  const int ne = E0 * E1 * E2;
+  for (int e = tid; e < ne; e += blockDim.x) {
+    const int ix = e % E0;
+    const int r = e / E0;
+    const int iy = r % E1;
+    const int iz = r / E1;
+    const int gx = wrapi(e0x + ix, g.M[0]), gy = wrapi(e0y + iy, g.M[1]), gz = wrapi(e0z + iz, g.M[2]);
+    ext[e] = field[((size_t)gz * g.M[1] + gy) * g.M[0] + gx];
+  }
+  __syncthreads();
+  const int tile = blockIdx.x;
+  const int a0 = off_t[tile * kTileBins], a1 = off_t[tile * kTileBins + kTileBins];
+  R(*ws)[P] = wsh[tid];
+  for (int j = a0 + tid; j < a1; j += blockDim.x) {
+    const real4<R> v = part[j];
+    const R s[3] = {v.x, v.y, v.z};
+    int l[3];
+    R wx[P], dx[P];
+    {
+      R wy[P], wz[P], dy[P], dz[P];
+      R fl = floor(s[0]);
+      l[0] = (int)fl - t0[0];
+      if (GRAD) bspline_d<R, P>(s[0] - fl, wx, dx); else bspline<R, P>(s[0] - fl, wx);
+      fl = floor(s[1]);
+      l[1] = (int)fl - t0[1];
+      if (GRAD) bspline_d<R, P>(s[1] - fl, wy, dy); else bspline<R, P>(s[1] - fl, wy);
+      fl = floor(s[2]);
+      l[2] = (int)fl - t0[2];
+      if (GRAD) bspline_d<R, P>(s[2] - fl, wz, dz); else bspline<R, P>(s[2] - fl, wz);
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        ws[0][k] = wy[k];
+        ws[1][k] = wz[k];
+        if (GRAD) {
+          ws[2][k] = dy[k];
+          ws[3][k] = dz[k];
+        }
+      }
+    }
+    R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
+#pragma unroll 2
+    for (int r = 0; r < P * P; ++r) {
+      const int jz = r / P, jy = r - jz * P;
+      const real4<R> *row = ext + ((l[2] + jz) * E1 + (l[1] + jy)) * E0 + l[0];
+      if (!GRAD) {
+        const R wzy = ws[1][jz] * ws[0][jy];
+#pragma unroll
+        for (int jx = 0; jx < P; ++jx) {
+          const real4<R> f = row[jx];
+          const R w = wzy * wx[jx];
+          a0s += w * f.x;
+          a1s += w * f.y;
+          a2s += w * f.z;
+          a3s += w * f.w;
+        }
+      } else {
+        const R wz_ = ws[1][jz], wy_ = ws[0][jy], dz_ = ws[3][jz], dy_ = ws[2][jy];
+        const R wzy = wz_ * wy_, dzy = dz_ * wy_, wzdy = wz_ * dy_;
+#pragma unroll
+        for (int jx = 0; jx < P; ++jx) {
+          const R psi = row[jx].w;
+          a0s += wzy * dx[jx] * psi;
+          a1s += wzdy * wx[jx] * psi;
+          a2s += dzy * wx[jx] * psi;
+          a3s += wzy * wx[jx] * psi;
+        }
+      }
+    }
+    const int i = perm[j];
+    const R qi = v.w;
+    if (!GRAD) {
+      if (vec_out) {
+        vec_out[3 * i] = pref * qi * a0s;
+        vec_out[3 * i + 1] = pref * qi * a1s;
+        vec_out[3 * i + 2] = pref * qi * a2s;
+      }
+      if (sca_out) sca_out[i] = pref * a3s;
+    } else {
+      if (vec_out) {
+        const R c = gscale * pref * qi;
+        vec_out[3 * i] = c * R(g.M[0] / g.L[0]) * a0s;
+        vec_out[3 * i + 1] = c * R(g.M[1] / g.L[1]) * a1s;
+        vec_out[3 * i + 2] = c * R(g.M[2] / g.L[2]) * a2s;
+      }
+      if (sca_out) sca_out[i] = gscale * pref * a3s;
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // real-space pair sum on a linked-cell list (Eq. 17; gradient form of Eq. 29)
-// Thread per active particle (cell order); neighbour cells' charged ranges are
-// read directly (lanes of one wave share cells, so loads hit in cache).  Both
-// orderings of a pair are evaluated, so no atomics are needed.
+//
+// One workgroup per cell (cell side > r_c).  The charged particles of the
+// (up to) 27 neighbouring cells are staged through LDS in chunks; the cell's
+// own active particles are spread over the lanes, and when there are fewer of
+// them than lanes, several lane groups split each chunk and their partial sums
+// are combined in LDS.  Both orderings of a pair are evaluated (no atomics).
 //   MODE 0: out_vec (forces) += ke q_i f_i, out_sca (potential) += ke phi_i +
-//           self + background terms, energy partials.
+//           self + background terms, energy partial per cell.
 //   MODE 1: adjoint, out_vec (dE/dr) -= gscale ke q_i f_i, out_sca (dE/dq) +=
 //           gscale (ke phi_i + self + background).
 // --------------------------------------------------------------------------
+
+// erfc(x) given e = exp(-x^2).  Single precision uses the five-term rational
+// approximation of Abramowitz & Stegun, Handbook of Mathematical Functions,
+// eq. 7.1.26 (absolute error <= 1.5e-7, below FP32 resolution of the force
+// sums), which reuses the exponential the force needs anyway; double precision
+// calls the device library's erfc.
+__device__ __forceinline__ float erfc_with_exp(float x, float e) {
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
+                                                                                     t * 1.061405429f))));
+  return poly * e;
+}
+__device__ __forceinline__ double erfc_with_exp(double x, double) { return erfc(x); }
+__device__ __forceinline__ float exp_fast(float v) { return __expf(v); }
+__device__ __forceinline__ double exp_fast(double v) { return exp(v); }
+
 template <typename R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_pair(const real4<R> *__restrict__ part, const int *__restrict__ perm,
-                                                 const int *__restrict__ off_c, const int *__restrict__ counts,
-                                                 Geom g, const double *__restrict__ scal, R gscale,
-                                                 R *__restrict__ out_vec, R *__restrict__ out_sca,
-                                                 double *rpart) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict__ part,
+                                                     const int *__restrict__ perm,
+                                                     const int *__restrict__ off_c, Geom g,
+                                                     const double *__restrict__ scal, R gscale,
+                                                     R *__restrict__ out_vec, R *__restrict__ out_sca,
+                                                     double *rpart) {
+  __shared__ real4<R> cand[kPairChunk];
+  __shared__ R red[kPairBlock][4];
+  __shared__ int rs[27], rp[28];
+  const int tid = threadIdx.x;
+  const int cell = blockIdx.x;
+  const int cx = cell % g.nc[0];
+  const int cy = (cell / g.nc[0]) % g.nc[1];
+  const int cz = cell / (g.nc[0] * g.nc[1]);
+  if (tid < 27) {
+    const int o[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+    const int cc[3] = {cx, cy, cz};
+    bool ok = true;
+    int nb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (g.nc[d] == 1) ok = ok && o[d] == 0;
+      else if (g.nc[d] == 2) ok = ok && o[d] >= 0;
+      nb[d] = (cc[d] + o[d] + g.nc[d]) % g.nc[d];
+    }
+    int s0 = 0, len = 0;
+    if (ok) {
+      const int cid = (nb[2] * g.nc[1] + nb[1]) * g.nc[0] + nb[0];
+      s0 = off_c[2 * cid];
+      len = off_c[2 * cid + 1] - s0;  // charged particles only
+    }
+    rs[tid] = s0;
+    rp[tid + 1] = len;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rp[0] = 0;
+    for (int k = 0; k < 27; ++k) rp[k + 1] += rp[k];
+  }
+  __syncthreads();
+  const int ncand = rp[27];
+  const int h0 = off_c[2 * cell], h1 = off_c[2 * cell + 2];  // all active particles of the cell
+  const R L0 = (R)g.L[0], L1 = (R)g.L[1], L2 = (R)g.L[2];
+  const R iL0 = (R)(1.0 / g.L[0]), iL1 = (R)(1.0 / g.L[1]), iL2 = (R)(1.0 / g.L[2]);
+  const R rc2 = (R)(g.rc * g.rc);
+  const R al = (R)g.alpha, al2 = (R)(g.alpha * g.alpha);
+  const R c2a = (R)(2.0 * g.alpha / 1.7724538509055160272981674833411);
+  const double V = g.L[0] * g.L[1] * g.L[2];
+  const double phi_bg = -g.ke * 3.14159265358979323846 * scal[0] / (V * g.alpha * g.alpha);
+  const double c_self = -2.0 * g.ke * g.alpha / 1.7724538509055160272981674833411;
   double e = 0.0;
-  if (j < counts[0]) {
-    const real4<R> v = part[j];
-    const R xi = v.x, yi = v.y, zi = v.z, qi = v.w;
-    const R L0 = (R)g.L[0], L1 = (R)g.L[1], L2 = (R)g.L[2];
-    const R iL0 = (R)(1.0 / g.L[0]), iL1 = (R)(1.0 / g.L[1]), iL2 = (R)(1.0 / g.L[2]);
-    const R rc2 = (R)(g.rc * g.rc);
-    const R al = (R)g.alpha, al2 = (R)(g.alpha * g.alpha);
-    const R c2a = (R)(2.0 * g.alpha / 1.7724538509055160272981674833411);
-    int cc[3];
-    const R pos[3] = {xi, yi, zi};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int c = (int)(pos[d] * R(g.nc[d] / g.L[d]));  // same expression as k_prep
-      cc[d] = c < g.nc[d] ? c : g.nc[d] - 1;
-    }
-    int no[3], o0[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (g.nc[d] >= 3) { no[d] = 3; o0[d] = -1; }
-      else { no[d] = g.nc[d]; o0[d] = 0; }
-    }
+
+  for (int hb = h0; hb < h1; hb += blockDim.x) {
+    const int nh = min((int)blockDim.x, h1 - hb);
+    const int G = blockDim.x / nh;
+    const int hi = tid % nh, grp = tid / nh;
+    const bool act = grp < G;
+    real4<R> me;
+    if (act) me = part[hb + hi];
     R fx = 0, fy = 0, fz = 0, ph = 0;
-    for (int a = 0; a < no[2]; ++a) {
-      const int cz = (cc[2] + o0[2] + a + g.nc[2]) % g.nc[2];
-      for (int b = 0; b < no[1]; ++b) {
-        const int cy = (cc[1] + o0[1] + b + g.nc[1]) % g.nc[1];
-        for (int c = 0; c < no[0]; ++c) {
-          const int cx = (cc[0] + o0[0] + c + g.nc[0]) % g.nc[0];
-          const int cid = (cz * g.nc[1] + cy) * g.nc[0] + cx;
-          const int s = off_c[2 * cid], t = off_c[2 * cid + 1];
-          for (int k = s; k < t; ++k) {
-            const real4<R> u = part[k];
-            R ddx = xi - u.x, ddy = yi - u.y, ddz = zi - u.z;
-            ddx -= L0 * rint(ddx * iL0);
-            ddy -= L1 * rint(ddy * iL1);
-            ddz -= L2 * rint(ddz * iL2);
-            const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            if (r2 < rc2 && r2 > R(0)) {
-              const R r = sqrt(r2);
-              const R ir = R(1) / r;
-              const R ec = erfc(al * r) * ir;
-              const R fs = u.w * (ec + c2a * exp(-al2 * r2)) * ir * ir;
-              ph += u.w * ec;
-              fx += fs * ddx;
-              fy += fs * ddy;
-              fz += fs * ddz;
-            }
+    for (int c0 = 0; c0 < ncand; c0 += kPairChunk) {
+      const int nc = min(kPairChunk, ncand - c0);
+      __syncthreads();
+      // stage candidates c0 .. c0+nc-1 range by range (no per-candidate search)
+      for (int r = 0; r < 27; ++r) {
+        const int lo = max(rp[r], c0), hi2 = min(rp[r + 1], c0 + nc);
+        for (int c = lo + tid; c < hi2; c += blockDim.x) cand[c - c0] = part[rs[r] + (c - rp[r])];
+      }
+      __syncthreads();
+      if (act) {
+        for (int k = grp; k < nc; k += G) {
+          const real4<R> u = cand[k];
+          R ddx = me.x - u.x, ddy = me.y - u.y, ddz = me.z - u.z;
+          ddx -= L0 * rint(ddx * iL0);
+          ddy -= L1 * rint(ddy * iL1);
+          ddz -= L2 * rint(ddz * iL2);
+          const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (r2 < rc2 && r2 > R(0)) {
+            const R ir = rsqrt(r2);
+            const R r = r2 * ir;
+            const R ex = exp_fast(-al2 * r2);
+            const R ec = erfc_with_exp(al * r, ex) * ir;
+            const R fs = u.w * (ec + c2a * ex) * ir * ir;
+            ph += u.w * ec;
+            fx += fs * ddx;
+            fy += fs * ddy;
+            fz += fs * ddz;
           }
         }
       }
     }
-    const double ke = g.ke;
-    e = 0.5 * (double)qi * (double)ph;
-    const int i = perm[j];
-    const double V = g.L[0] * g.L[1] * g.L[2];
-    const double phs = ke * (double)ph - 2.0 * ke * g.alpha / 1.7724538509055160272981674833411 * (double)qi -
-                       ke * 3.14159265358979323846 * scal[0] / (V * g.alpha * g.alpha);
-    if (MODE == 0) {
-      if (out_vec) {
-        const R c = (R)ke * qi;
-        out_vec[3 * i] += c * fx;
-        out_vec[3 * i + 1] += c * fy;
-        out_vec[3 * i + 2] += c * fz;
+    // combine the lane groups of each home particle
+    __syncthreads();
+    red[tid][0] = fx;
+    red[tid][1] = fy;
+    red[tid][2] = fz;
+    red[tid][3] = ph;
+    __syncthreads();
+    if (act && grp == 0) {
+      for (int k = 1; k < G; ++k) {
+        fx += red[k * nh + hi][0];
+        fy += red[k * nh + hi][1];
+        fz += red[k * nh + hi][2];
+        ph += red[k * nh + hi][3];
       }
-      if (out_sca) out_sca[i] += (R)phs;
-    } else {
-      if (out_vec) {
-        const R c = -gscale * (R)ke * qi;
-        out_vec[3 * i] += c * fx;
-        out_vec[3 * i + 1] += c * fy;
-        out_vec[3 * i + 2] += c * fz;
+      const R qi = me.w;
+      e += 0.5 * (double)qi * (double)ph;
+      const int i = perm[hb + hi];
+      const double phs = g.ke * (double)ph + c_self * (double)qi + phi_bg;
+      if (MODE == 0) {
+        if (out_vec) {
+          const R c = (R)g.ke * qi;
+          out_vec[3 * i] += c * fx;
+          out_vec[3 * i + 1] += c * fy;
+          out_vec[3 * i + 2] += c * fz;
+        }
+        if (out_sca) out_sca[i] += (R)phs;
+      } else {
+        if (out_vec) {
+          const R c = -gscale * (R)g.ke * qi;
+          out_vec[3 * i] += c * fx;
+          out_vec[3 * i + 1] += c * fy;
+          out_vec[3 * i + 2] += c * fz;
+        }
+        if (out_sca) out_sca[i] += gscale * (R)phs;
       }
-      if (out_sca) out_sca[i] += gscale * (R)phs;
     }
   }
   if (MODE == 0) {
     const double tot = block_sum(e);
-    if (threadIdx.x == 0) rpart[blockIdx.x] = tot;
+    if (tid == 0) rpart[blockIdx.x] = tot;
   }
 }
 
 // energy parts in FP64: (total, E_R, E_K, E_self, E_bg)
-__global__ __launch_bounds__(256) void k_finalize(const double *kpart, int nk, const double *rpart, int nr,
+__global__ __launch_bounds__(1024) void k_finalize(const double *kpart, int nk, const double *rpart, int nr,
                                                   const double *scal, Geom g, double *E) {
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nk; i += blockDim.x) a += kpart[i];
@@ -929,7 +1195,55 @@ __global__ __launch_bounds__(256) void k_finalize(const double *kpart, int nk, c
 // host side: tables and launch sequences
 // --------------------------------------------------------------------------
 int nblk_prep(const Geom &g) { return (g.n + kBlock - 1) / kBlock; }
-int nblk_pair(const Geom &g) { return (g.n + kBlock - 1) / kBlock; }
+int nblk_pair(const Geom &g) { return g.ncells; }
+static int scan_bt(const Geom &g) { return (kTileBins * g.ntiles + kScanChunk - 1) / kScanChunk; }
+static int scan_bc(const Geom &g) { return (2 * g.ncells + kScanChunk - 1) / kScanChunk; }
+int nblk_scan(const Geom &g) { return scan_bt(g) + scan_bc(g); }
+
+int build_runs(const Geom &g, int *out) {
+  int n = 0;
+  int offs[3][3], no[3];
+  for (int d = 0; d < 3; ++d) {
+    if (g.nt[d] >= 3) { offs[d][0] = -1; offs[d][1] = 0; offs[d][2] = 1; no[d] = 3; }
+    else { offs[d][0] = 0; offs[d][1] = 1; no[d] = 2; }
+  }
+  // digits a particle of the neighbour at offset o must have on one axis to
+  // reach the consuming tile: above it (o=+1) it must cross its low face (0),
+  // below it (o=-1) its high face (2); with two tiles per axis the single
+  // neighbour is on both sides
+  auto allowed = [&](int d, int o, int dig) {
+    if (o == 0) return true;
+    if (g.nt[d] == 2) return dig != 1;
+    return o > 0 ? dig == 0 : dig == 2;
+  };
+  for (int a = 0; a < no[2]; ++a)
+    for (int b = 0; b < no[1]; ++b)
+      for (int c = 0; c < no[0]; ++c) {
+        const int o[3] = {offs[0][c], offs[1][b], offs[2][a]};
+        int lo = -1, prev = -2;
+        for (int cl = 0; cl < kClasses; ++cl) {
+          const int dx = cl / 9, dy = (cl / 3) % 3, dz = cl % 3;
+          const bool ok = allowed(0, o[0], dx) && allowed(1, o[1], dy) && allowed(2, o[2], dz);
+          if (ok) {
+            if (prev != cl - 1) lo = cl;
+            prev = cl;
+          }
+          const bool close = lo >= 0 && prev == cl && (cl == kClasses - 1 || !(
+              allowed(0, o[0], (cl + 1) / 9) && allowed(1, o[1], ((cl + 1) / 3) % 3) && allowed(2, o[2], (cl + 1) % 3)));
+          if (close) {
+            if (n >= kMaxRuns) return -1;
+            out[5 * n] = o[0];
+            out[5 * n + 1] = o[1];
+            out[5 * n + 2] = o[2];
+            out[5 * n + 3] = lo;
+            out[5 * n + 4] = cl;
+            ++n;
+            lo = -1;
+          }
+        }
+      }
+  return n;
+}
 
 // pencils per block for a pass so that `per_pencil` bytes * nb <= budget,
 // nb a power of two dividing `count`, at most 16
@@ -1008,12 +1322,29 @@ template void fill_tables<double>(const Geom &, const size_t[8], double *);
 
 template <typename R, int P>
 static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(kBlock), 0, st,
-                     (const real4<R> *)w.part_t, w.off_t, g, (R *)w.grid);
+  hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(spread_block<R>()), 0, st,
+                     (const real4<R> *)w.part_t, w.off_t, (const int *)w.runs, w.nruns, g, (R *)w.grid);
+}
+template <typename R, int P>
+static size_t gather_tile_lds(const Geom &g) {
+  return (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1) * sizeof(real4<R>);
 }
 template <typename R, int P>
 static void launch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R *vo, R *so,
                           bool grad) {
+  const size_t lds = gather_tile_lds<R, P>(g);
+  const size_t stat = (size_t)kGatherBlock * (grad ? 4 : 2) * P * sizeof(R);
+  if (lds + stat <= 65536) {
+    if (grad)
+      hipLaunchKernelGGL((k_gather_tile<R, P, true>), dim3(g.ntiles), dim3(kGatherBlock), lds, st,
+                         (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const real4<R> *)w.field, pref, gs,
+                         vo, so);
+    else
+      hipLaunchKernelGGL((k_gather_tile<R, P, false>), dim3(g.ntiles), dim3(kGatherBlock), lds, st,
+                         (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const real4<R> *)w.field, pref, gs,
+                         vo, so);
+    return;
+  }
   const int nb = (g.n + kGatherBlock - 1) / kGatherBlock;
   if (grad)
     hipLaunchKernelGGL((k_gather<R, P, true>), dim3(nb), dim3(kGatherBlock), 0, st, (const real4<R> *)w.part_t,
@@ -1044,7 +1375,7 @@ static void dispatch_gather(const Geom &g, const Work &w, hipStream_t st, R pref
 
 template <typename R>
 hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R *x, const R *q, double *E,
-                          R *F, R *phi, bool all_active, hipEvent_t *ev) {
+                          R *F, R *phi, bool all_active, bool want_psi, hipEvent_t *ev) {
   const size_t cs = sizeof(Cx<R>);
   const R *tab = (const R *)w.tables;
   const Cx<R> *tw_xh = (const Cx<R> *)(tab + w.tab_off[0]);
@@ -1054,19 +1385,30 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   const R *cwx = tab + w.tab_off[4], *cwy = tab + w.tab_off[5], *cwz = tab + w.tab_off[6];
   const int hx = g.M[0] / 2;
   const size_t halfG = (size_t)hx * g.M[1] * g.M[2];
+  // the potential field psi is transformed only when potentials (or a later
+  // adjoint) need it; forces use the three ik fields
+  const int nfield = want_psi ? 4 : 3;
   auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
 
   mark(0);
   // prep
-  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(kBlock), 0, st, w.off_t, 2 * g.ntiles + 1, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(kBlock), 0, st, w.off_c, 2 * g.ncells + 1, 0);
+  const int nbt = kTileBins * g.ntiles, nbc = 2 * g.ncells;
+  hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(kBlock), 0, st, w.off_t, nbt + 1, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(kBlock), 0, st, w.off_c, nbc + 1, 0);
   hipLaunchKernelGGL((k_prep<R>), dim3(nblk_prep(g)), dim3(kBlock), 0, st, x, q, g, all_active ? 1 : 0,
                      w.key_t, w.rank_t, w.key_c, w.rank_c, w.off_t, w.off_c, F, phi, w.qpart, w.counts);
   ENUF_TRY(hipGetLastError());
   mark(1);
   // sort
-  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, st, w.off_t, 2 * g.ntiles, w.off_c, 2 * g.ncells,
-                     (const double *)w.qpart, nblk_prep(g), w.scal, w.counts);
+  {
+    const int bt = scan_bt(g), bc = scan_bc(g);
+    hipLaunchKernelGGL(k_scan1, dim3(bt + bc), dim3(kScanBlock), 0, st, w.off_t, nbt, w.off_c, nbc, bt, w.bsum,
+                       w.bev);
+    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(1024), 0, st, w.bsum, (const int *)w.bev, bt, bc, w.off_t, nbt,
+                       w.off_c, nbc, (const double *)w.qpart, nblk_prep(g), w.scal, w.counts);
+    hipLaunchKernelGGL(k_scan3, dim3(bt + bc), dim3(kScanBlock), 0, st, w.off_t, nbt, w.off_c, nbc, bt,
+                       (const int *)w.bsum);
+  }
   hipLaunchKernelGGL((k_scatter<R>), dim3(nblk_prep(g)), dim3(kBlock), 0, st, x, q, g, w.key_t, w.rank_t,
                      w.key_c, w.rank_c, w.off_t, w.off_c, (real4<R> *)w.part_t, w.perm_t,
                      (real4<R> *)w.part_c, w.perm_c);
@@ -1092,19 +1434,19 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
     const int nb = nb_z(g, cs);
     const size_t sh = (size_t)g.M[2] * nb * (3 * cs + sizeof(R));
     hipLaunchKernelGGL((k_z_fused<R>), dim3(hx * g.M[1] / nb), dim3(kBlock), sh, st,
-                       (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, tw_z, cwx, cwy, cwz, w.kpart, nb);
+                       (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, tw_z, cwx, cwy, cwz, w.kpart, nb, nfield);
   }
   ENUF_TRY(hipGetLastError());
   mark(5);
   // inverse y (4 components), inverse x c2r -> interleaved fields
   {
     const int nby = nb_axis(g.M[1], hx, cs);
-    hipLaunchKernelGGL((k_fft_axis<R, 1>), dim3(hx / nby, g.M[2], 4), dim3(kBlock), 2 * g.M[1] * nby * cs,
+    hipLaunchKernelGGL((k_fft_axis<R, 1>), dim3(hx / nby, g.M[2], nfield), dim3(kBlock), 2 * g.M[1] * nby * cs,
                        st, (Cx<R> *)w.fspec, g.M[1], hx, (size_t)hx * g.M[1], halfG, tw_y, nby);
     const int nb = nb_xc2r(g, cs);
     const size_t sh = 2 * (size_t)hx * nb * cs + (size_t)nb * g.M[0] * 4 * sizeof(R);
     hipLaunchKernelGGL((k_fft_x_c2r4<R>), dim3(g.M[1] * g.M[2] / nb), dim3(kBlock), sh, st,
-                       (const Cx<R> *)w.fspec, (real4<R> *)w.field, g, tw_xh, tw_x2, nb);
+                       (const Cx<R> *)w.fspec, (real4<R> *)w.field, g, tw_xh, tw_x2, nb, nfield);
   }
   ENUF_TRY(hipGetLastError());
   mark(6);
@@ -1115,11 +1457,11 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   ENUF_TRY(hipGetLastError());
   mark(7);
   // pair
-  hipLaunchKernelGGL((k_pair<R, 0>), dim3(nblk_pair(g)), dim3(kBlock), 0, st, (const real4<R> *)w.part_c,
-                     w.perm_c, w.off_c, w.counts, g, w.scal, R(1), F, phi, w.rpart);
+  hipLaunchKernelGGL((k_pair<R, 0>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
+                     w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
   ENUF_TRY(hipGetLastError());
   mark(8);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double *)w.kpart,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, (const double *)w.kpart,
                      nblk_z(g, sizeof(R) == 8), (const double *)w.rpart, nblk_pair(g), (const double *)w.scal, g,
                      E);
   ENUF_TRY(hipGetLastError());
@@ -1136,15 +1478,15 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
   const R pref = (R)(g.ke * 4.0 * 3.14159265358979323846 / V);
   dispatch_gather<R>(g, w, st, pref, (R)gscale, dEdx, dEdq, true);
   ENUF_TRY(hipGetLastError());
-  hipLaunchKernelGGL((k_pair<R, 1>), dim3(nblk_pair(g)), dim3(kBlock), 0, st, (const real4<R> *)w.part_c,
-                     w.perm_c, w.off_c, w.counts, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
+  hipLaunchKernelGGL((k_pair<R, 1>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
+                     w.perm_c, w.off_c, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
   return hipGetLastError();
 }
 
 template hipError_t launch_forward<float>(const Geom &, const Work &, hipStream_t, const float *, const float *,
-                                          double *, float *, float *, bool, hipEvent_t *);
+                                          double *, float *, float *, bool, bool, hipEvent_t *);
 template hipError_t launch_forward<double>(const Geom &, const Work &, hipStream_t, const double *,
-                                           const double *, double *, double *, double *, bool, hipEvent_t *);
+                                           const double *, double *, double *, double *, bool, bool, hipEvent_t *);
 template hipError_t launch_adjoint<float>(const Geom &, const Work &, hipStream_t, double, float *, float *);
 template hipError_t launch_adjoint<double>(const Geom &, const Work &, hipStream_t, double, double *, double *);
 

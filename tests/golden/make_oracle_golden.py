@@ -1,0 +1,56 @@
+"""Write stored oracle values for the benchmark workloads.
+
+    python tests/golden/make_oracle_golden.py [workload ...]
+
+Calls only the direct FP64 Ewald oracle (oracle/ewald.py) on the seeded
+synthetic workloads and writes tests/golden/<workload>_oracle.npz with the
+energy parts and the forces/potentials of a seeded sample of charged
+particles.  The k-space sum runs over every k with exp(-k^2/4 alpha^2) >= tol.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import ewald  # noqa: E402
+from paper_2004_12484_amd import inputs  # noqa: E402
+
+# workload -> (generator kwargs, sample size or None for all charged, k-space tolerance)
+SPECS = {
+    "nacl": (dict(), None, 1e-16),
+    "electrolyte": (dict(), 2048, 1e-16),
+    "charged_fluid": (dict(alpha=0.95), 512, 1e-10),
+}
+
+
+def make(name):
+    kw, ns, tol = SPECS[name]
+    w = getattr(inputs, name)(**kw)
+    charged = np.nonzero(w.q)[0]
+    if ns is None or ns >= len(charged):
+        sample = charged
+    else:
+        sample = np.sort(np.random.default_rng(123).choice(charged, ns, replace=False))
+    t = time.time()
+    r = ewald.ewald(w.x, w.q, w.box, w.alpha, w.r_c, w.ke, tol=tol, sample=sample)
+    # the same sum with the real-space cut pushed out until erfc(alpha r) < 1e-10
+    # (forces only): the difference is the truncation error of r_c itself
+    rc_conv = min(0.5 * float(np.min(w.box)), 4.6 / w.alpha)
+    _, f_rc, _ = ewald.real_minimage(w.x, w.q, w.box, w.alpha, rc_conv, w.ke, sample=sample)
+    dt = time.time() - t
+    path = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(path, sample=sample.astype(np.int64), F=r["F"], F_K=r["F_K"], phi=r["phi"],
+                        E=r["E"], E_R=r["E_R"], E_K=r["E_K"], E_self=r["E_self"], E_bg=r["E_bg"],
+                        F_conv=f_rc + r["F_K"], rc_conv=rc_conv,
+                        alpha=w.alpha, r_c=w.r_c, N=w.N, seed=w.seed, tol=tol)
+    print(f"{name}: E={r['E']:.12g} sample={len(sample)} oracle {dt:.1f} s -> {path}", flush=True)
+
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or list(SPECS)):
+        make(n)

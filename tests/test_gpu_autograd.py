@@ -115,3 +115,23 @@ def test_grad_before_forward_is_state_error():
     with pytest.raises(enuf.EnufError) as ei:
         eng.energy_grad(1.0)
     assert ei.value.status == enuf.ENUF_ESTATE
+
+
+def test_grad_after_forces_only_forward_is_state_error():
+    x, q, box = _sys(n=300, seed=15)
+    eng, out = run(x, q, box, 1.1, 4.0, (32, 32, 32), 4, potential=False)
+    with pytest.raises(enuf.EnufError) as ei:
+        eng.energy_grad(1.0)
+    assert ei.value.status == enuf.ENUF_ESTATE
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_forces_only_matches_forces_with_potential(prec):
+    # three-field and four-field evaluations give the same forces and energy
+    x, q, box = _sys(n=800, seed=16)
+    eng, a = run(x, q, box, 1.1, 4.0, (32, 32, 32), 6, precision=prec, potential=True)
+    _, b = run(x, q, box, 1.1, 4.0, (32, 32, 32), 6, precision=prec, potential=False, eng=eng)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert np.abs(a["E"] - b["E"]).max() <= tol * np.abs(a["E"]).max()
+    # neutral sites are active only with potentials; forces on them are zero either way
+    assert rms_rel(b["F"], a["F"]) <= tol
