@@ -897,14 +897,13 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
 // interpolates every active particle of the tile from LDS.  Used when the
 // staged tile fits the LDS budget; same outputs as k_gather.
 template <typename R, int P, bool GRAD>
-__global__ __launch_bounds__(kGatherBlock) void k_gather_tile(const real4<R> *__restrict__ part,
-                                                              const int *__restrict__ perm,
-                                                              const int *__restrict__ off_t, Geom g,
-                                                              const real4<R> *__restrict__ field, R pref,
-                                                              R gscale, R *__restrict__ vec_out,
-                                                              R *__restrict__ sca_out) {
+__global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
+                                                                  const int *__restrict__ perm,
+                                                                  const int *__restrict__ off_t, Geom g,
+                                                                  const real4<R> *__restrict__ field, R pref,
+                                                                  R gscale, R *__restrict__ vec_out,
+                                                                  R *__restrict__ sca_out) {
   extern __shared__ unsigned char smem_raw[];
-  __shared__ R wsh[kGatherBlock][GRAD ? 4 : 2][P];
   real4<R> *ext = reinterpret_cast<real4<R> *>(smem_raw);
   const int tid = threadIdx.x;
   int t = blockIdx.x;
@@ -915,8 +914,9 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather_tile(const real4<R> *__
   const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
   const int E0 = g.T[0] + P - 1, E1 = g.T[1] + P - 1, E2 = g.T[2] + P - 1;
   const int e0x = t0[0] - P / 2 + 1, e0y = t0[1] - P / 2 + 1, e0z = t0[2] - P / 2 + 1;
-  const int ne = E0 * E1 * E2;
-  for (int e = tid; e < ne; e += blockDim.x) {
+  const int nrow = E1 * E2;
+  // one thread per (row, x) with the rows of E0 points loaded contiguously
+  for (int e = tid; e < nrow * E0; e += blockDim.x) {
     const int ix = e % E0;
     const int r = e / E0;
     const int iy = r % E1;
@@ -927,40 +927,31 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather_tile(const real4<R> *__
   __syncthreads();
   const int tile = blockIdx.x;
   const int a0 = off_t[tile * kTileBins], a1 = off_t[tile * kTileBins + kTileBins];
-  R(*ws)[P] = wsh[tid];
   for (int j = a0 + tid; j < a1; j += blockDim.x) {
     const real4<R> v = part[j];
-    const R s[3] = {v.x, v.y, v.z};
     int l[3];
-    R wx[P], dx[P];
+    R wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
     {
-      R wy[P], wz[P], dy[P], dz[P];
-      R fl = floor(s[0]);
+      R fl = floor(v.x);
       l[0] = (int)fl - t0[0];
-      if (GRAD) bspline_d<R, P>(s[0] - fl, wx, dx); else bspline<R, P>(s[0] - fl, wx);
-      fl = floor(s[1]);
+      if (GRAD) bspline_d<R, P>(v.x - fl, wx, dx); else bspline<R, P>(v.x - fl, wx);
+      fl = floor(v.y);
       l[1] = (int)fl - t0[1];
-      if (GRAD) bspline_d<R, P>(s[1] - fl, wy, dy); else bspline<R, P>(s[1] - fl, wy);
-      fl = floor(s[2]);
+      if (GRAD) bspline_d<R, P>(v.y - fl, wy, dy); else bspline<R, P>(v.y - fl, wy);
+      fl = floor(v.z);
       l[2] = (int)fl - t0[2];
-      if (GRAD) bspline_d<R, P>(s[2] - fl, wz, dz); else bspline<R, P>(s[2] - fl, wz);
-#pragma unroll
-      for (int k = 0; k < P; ++k) {
-        ws[0][k] = wy[k];
-        ws[1][k] = wz[k];
-        if (GRAD) {
-          ws[2][k] = dy[k];
-          ws[3][k] = dz[k];
-        }
-      }
+      if (GRAD) bspline_d<R, P>(v.z - fl, wz, dz); else bspline<R, P>(v.z - fl, wz);
     }
     R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
-#pragma unroll 2
+    const real4<R> *base = ext + (l[2] * E1 + l[1]) * E0 + l[0];
+    // rolled (z, y) row loop: the row index is uniform across the wave, so
+    // the weight arrays are indexed without spilling them
+#pragma unroll 1
     for (int r = 0; r < P * P; ++r) {
       const int jz = r / P, jy = r - jz * P;
-      const real4<R> *row = ext + ((l[2] + jz) * E1 + (l[1] + jy)) * E0 + l[0];
+      const real4<R> *row = base + (jz * E1 + jy) * E0;
       if (!GRAD) {
-        const R wzy = ws[1][jz] * ws[0][jy];
+        const R wzy = wz[jz] * wy[jy];
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
           const real4<R> f = row[jx];
@@ -971,8 +962,7 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather_tile(const real4<R> *__
           a3s += w * f.w;
         }
       } else {
-        const R wz_ = ws[1][jz], wy_ = ws[0][jy], dz_ = ws[3][jz], dy_ = ws[2][jy];
-        const R wzy = wz_ * wy_, dzy = dz_ * wy_, wzdy = wz_ * dy_;
+        const R wzy = wz[jz] * wy[jy], dzy = dz[jz] * wy[jy], wzdy = wz[jz] * dy[jy];
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
           const R psi = row[jx].w;
@@ -1097,10 +1087,16 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
     for (int c0 = 0; c0 < ncand; c0 += kPairChunk) {
       const int nc = min(kPairChunk, ncand - c0);
       __syncthreads();
-      // stage candidates c0 .. c0+nc-1 range by range (no per-candidate search)
-      for (int r = 0; r < 27; ++r) {
-        const int lo = max(rp[r], c0), hi2 = min(rp[r + 1], c0 + nc);
-        for (int c = lo + tid; c < hi2; c += blockDim.x) cand[c - c0] = part[rs[r] + (c - rp[r])];
+      // stage candidates c0 .. c0+nc-1: every thread finds the range of its
+      // candidates by binary search, so all global loads are in flight at once
+      for (int k = tid; k < nc; k += blockDim.x) {
+        const int c = c0 + k;
+        int lo = 0, hi2 = 27;
+        while (hi2 - lo > 1) {
+          const int mid = (lo + hi2) >> 1;
+          if (rp[mid] <= c) lo = mid; else hi2 = mid;
+        }
+        cand[k] = part[rs[lo] + (c - rp[lo])];
       }
       __syncthreads();
       if (act) {
@@ -1333,14 +1329,13 @@ template <typename R, int P>
 static void launch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R *vo, R *so,
                           bool grad) {
   const size_t lds = gather_tile_lds<R, P>(g);
-  const size_t stat = (size_t)kGatherBlock * (grad ? 4 : 2) * P * sizeof(R);
-  if (lds + stat <= 65536) {
+  if (lds <= 65536) {
     if (grad)
-      hipLaunchKernelGGL((k_gather_tile<R, P, true>), dim3(g.ntiles), dim3(kGatherBlock), lds, st,
+      hipLaunchKernelGGL((k_gather_tile<R, P, true>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
                          (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const real4<R> *)w.field, pref, gs,
                          vo, so);
     else
-      hipLaunchKernelGGL((k_gather_tile<R, P, false>), dim3(g.ntiles), dim3(kGatherBlock), lds, st,
+      hipLaunchKernelGGL((k_gather_tile<R, P, false>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
                          (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const real4<R> *)w.field, pref, gs,
                          vo, so);
     return;
