@@ -403,16 +403,20 @@ constexpr int spread_block() { return sizeof(R) == 8 ? 128 : 256; }
 
 template <typename R, int P>
 __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__restrict__ part,
-                                                   const int *__restrict__ off_t,
-                                                   const int *__restrict__ runs, int nruns, Geom g,
-                                                   R *__restrict__ grid) {
-  // one private accumulator per wavefront: a wave only ever adds one
-  // particle's (distinct) box points per instruction, so plain LDS
-  // read-modify-write is race free and avoids the slow LDS float atomics
+                                                              const int *__restrict__ off_t,
+                                                              const int *__restrict__ runs, int nruns, Geom g,
+                                                              R *__restrict__ grid) {
+  // One private accumulator per wavefront: a wave only ever adds the distinct
+  // box points of one particle per step, so plain LDS read-modify-write is
+  // race free (LDS float atomics are several times slower).
   constexpr int NB = spread_block<R>();
   __shared__ R acc[NB / 64][kMaxTilePts];
-  __shared__ R wst[NB][3][P];
-  __shared__ int box[NB][3];  // per axis: lstart | count << 8 | jstart << 16
+  // Per staged particle: its box in the tile as two "lane" axes A (outer),
+  // B (inner) and one "loop" axis C, the window weights along each (charge
+  // folded into C, entry 0 = first point inside the tile), and a descriptor
+  // {corner offset, nA | nB << 8 | nC << 16, strideA | strideB << 16, strideC}.
+  __shared__ R wA[NB][P], wB[NB][P], wC[NB][P];
+  __shared__ int4 desc[NB];
   __shared__ int rstart[kMaxRuns], rpre[kMaxRuns + 1];
   __shared__ int nstaged;
 
@@ -424,6 +428,7 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
   const int tz = t / g.nt[1];
   const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
   const int tpts = g.T[0] * g.T[1] * g.T[2];
+  const int sy = g.T[0], sz = g.T[0] * g.T[1];
   for (int e = tid; e < tpts; e += blockDim.x)
 #pragma unroll
     for (int k = 0; k < NB / 64; ++k) acc[k][e] = R(0);
@@ -431,9 +436,9 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
   // runs -> particle ranges, then an exclusive prefix over their lengths
   for (int k = tid; k < nruns; k += blockDim.x) {
     const int *rr = runs + 5 * k;
-    const int nx = (tx + rr[0] + g.nt[0]) % g.nt[0];
-    const int ny = (ty + rr[1] + g.nt[1]) % g.nt[1];
-    const int nz = (tz + rr[2] + g.nt[2]) % g.nt[2];
+    const int nx = wrapi(tx + rr[0], g.nt[0]);
+    const int ny = wrapi(ty + rr[1], g.nt[1]);
+    const int nz = wrapi(tz + rr[2], g.nt[2]);
     const int tt = (nz * g.nt[1] + ny) * g.nt[0] + nx;
     const int s0 = off_t[tt * kTileBins + rr[3]];
     const int s1 = off_t[tt * kTileBins + rr[4] + 1];
@@ -460,13 +465,13 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
   __syncthreads();
   const int total = rpre[nruns];
   const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  R *my = acc[wv];
 
   for (int base = 0; base < total; base += blockDim.x) {
     if (tid == 0) nstaged = 0;
     __syncthreads();
     const int c = base + tid;
     if (c < total) {
-      // range holding candidate c (binary search over the run prefix)
       int lo = 0, hi = nruns;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -481,8 +486,11 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
       for (int d = 0; d < 3; ++d) {
         const R fl = floor(s[d]);
         fr[d] = s[d] - fl;
+        // stencil start relative to the tile, brought into [0, M)
         int rel = (int)fl - P / 2 + 1 - t0[d];
-        rel = ((rel % g.M[d]) + g.M[d]) % g.M[d];
+        if (rel < 0) rel += g.M[d];
+        if (rel < 0) rel += g.M[d];
+        if (rel >= g.M[d]) rel -= g.M[d];
         if (rel < g.T[d]) {
           ls[d] = rel;
           js[d] = 0;
@@ -496,36 +504,50 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
       }
       if (hit) {
         const int slot = atomicAdd(&nstaged, 1);
+        // loop over the shorter of z and x; lanes cover the other two axes
+        const bool loopz = cnt[2] <= cnt[0];
+        const int aA = loopz ? 1 : 2, aB = loopz ? 0 : 1, aC = loopz ? 2 : 0;
+        const int strd[3] = {1, sy, sz};
         R w[P];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           bspline<R, P>(fr[d], w);
-          const R sc = (d == 2) ? v.w : R(1);
+          const R sc = (d == aC) ? v.w : R(1);
+          R *dst = (d == aA) ? wA[slot] : ((d == aB) ? wB[slot] : wC[slot]);
 #pragma unroll
-          for (int j = 0; j < P; ++j) wst[slot][d][j] = w[j] * sc;
-          box[slot][d] = ls[d] | (cnt[d] << 8) | (js[d] << 16);
+          for (int j = 0; j < P; ++j)
+            if (j >= js[d] && j - js[d] < cnt[d]) dst[j - js[d]] = w[j] * sc;
         }
+        desc[slot] = make_int4(ls[2] * sz + ls[1] * sy + ls[0],
+                               cnt[aA] | (cnt[aB] << 8) | (cnt[aC] << 16),
+                               strd[aA] | (strd[aB] << 16), strd[aC]);
       }
     }
     __syncthreads();
     const int ns = nstaged;
-    R *my = acc[wv];
     for (int sp = wv; sp < ns; sp += nwv) {
-      const int bx = box[sp][0], by = box[sp][1], bz = box[sp][2];
-      const int lx = bx & 255, cx = (bx >> 8) & 255, jx = bx >> 16;
-      const int ly = by & 255, cy = (by >> 8) & 255, jy = by >> 16;
-      const int lz = bz & 255, cz = (bz >> 8) & 255, jz = bz >> 16;
-      const int cyx = cy * cx, npts = cz * cyx;
-      const float inv_yx = __builtin_amdgcn_rcpf((float)cyx), inv_x = __builtin_amdgcn_rcpf((float)cx);
-      const R *wz = wst[sp][2] + jz, *wy = wst[sp][1] + jy, *wx = wst[sp][0] + jx;
-      R *row0 = my + (lz * g.T[1] + ly) * g.T[0] + lx;
-      for (int pt = lane; pt < npts; pt += 64) {
-        const int iz = (int)(((float)pt + 0.5f) * inv_yx);
-        const int rem = pt - iz * cyx;
-        const int iy = (int)(((float)rem + 0.5f) * inv_x);
-        const int ix = rem - iy * cx;
-        R *a = row0 + (iz * g.T[1] + iy) * g.T[0] + ix;
-        *a += wz[iz] * wy[iy] * wx[ix];
+      // descriptor fields are the same for the whole wave: keep them scalar
+      const int4 dd = desc[sp];
+      const int corner = __builtin_amdgcn_readfirstlane(dd.x);
+      const int dims = __builtin_amdgcn_readfirstlane(dd.y);
+      const int st2 = __builtin_amdgcn_readfirstlane(dd.z);
+      const int sC = __builtin_amdgcn_readfirstlane(dd.w);
+      const int nA = dims & 255, nB = (dims >> 8) & 255, nC = dims >> 16;
+      const int sA = st2 & 0xffff, sB = st2 >> 16;
+      if (lane < nA * nB) {
+        const int a = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nB));
+        const int b = lane - __umul24(a, nB);
+        const R w2 = wA[sp][a] * wB[sp][b];
+        R *pa = my + corner + __umul24(a, sA) + __umul24(b, sB);
+        const R *wc = wC[sp];
+        // the nC points of this lane are distinct: read them all, then write
+        R vv[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+          if (k < nC) vv[k] = pa[k * sC];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+          if (k < nC) pa[k * sC] = vv[k] + w2 * wc[k];
       }
     }
     __syncthreads();
@@ -1022,8 +1044,10 @@ __device__ __forceinline__ float erfc_with_exp(float x, float e) {
 __device__ __forceinline__ double erfc_with_exp(double x, double) { return erfc(x); }
 __device__ __forceinline__ float exp_fast(float v) { return __expf(v); }
 __device__ __forceinline__ double exp_fast(double v) { return exp(v); }
+__device__ __forceinline__ float rsqrt_r(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double rsqrt_r(double v) { return 1.0 / sqrt(v); }
 
-template <typename R, int MODE>
+template <typename R, int MODE, bool MINIMG>
 __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict__ part,
                                                      const int *__restrict__ perm,
                                                      const int *__restrict__ off_c, Geom g,
@@ -1033,11 +1057,18 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
   __shared__ real4<R> cand[kPairChunk];
   __shared__ R red[kPairBlock][4];
   __shared__ int rs[27], rp[28];
+  __shared__ R rsh[27][3];  // periodic image shift of each neighbour cell
+  __shared__ int hrange[2];
   const int tid = threadIdx.x;
   const int cell = blockIdx.x;
   const int cx = cell % g.nc[0];
   const int cy = (cell / g.nc[0]) % g.nc[1];
   const int cz = cell / (g.nc[0] * g.nc[1]);
+  // with >= 3 cells on an axis the neighbour's image is fixed by the cell
+  // offset and is added while staging; with fewer, the minimum image is taken
+  // per pair on that axis
+  // MINIMG: some axis has fewer than 3 cells; only then is rint needed
+  const bool mi0 = MINIMG && g.nc[0] < 3, mi1 = MINIMG && g.nc[1] < 3, mi2 = MINIMG && g.nc[2] < 3;
   if (tid < 27) {
     const int o[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
     const int cc[3] = {cx, cy, cz};
@@ -1047,7 +1078,11 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
     for (int d = 0; d < 3; ++d) {
       if (g.nc[d] == 1) ok = ok && o[d] == 0;
       else if (g.nc[d] == 2) ok = ok && o[d] >= 0;
-      nb[d] = (cc[d] + o[d] + g.nc[d]) % g.nc[d];
+      const int v = cc[d] + o[d];
+      nb[d] = (v + g.nc[d]) % g.nc[d];
+      R sh = R(0);
+      if (g.nc[d] >= 3) sh = v < 0 ? -(R)g.L[d] : (v >= g.nc[d] ? (R)g.L[d] : R(0));
+      rsh[tid][d] = sh;
     }
     int s0 = 0, len = 0;
     if (ok) {
@@ -1058,14 +1093,21 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
     rs[tid] = s0;
     rp[tid + 1] = len;
   }
+  if (tid == 32) { hrange[0] = off_c[2 * cell]; hrange[1] = off_c[2 * cell + 2]; }
   __syncthreads();
-  if (tid == 0) {
-    rp[0] = 0;
-    for (int k = 0; k < 27; ++k) rp[k + 1] += rp[k];
+  if (tid < 32) {  // inclusive prefix over the 27 lengths in one wave
+    int v = (tid < 27) ? rp[tid + 1] : 0;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int u = __shfl_up(v, o, 64);
+      if (tid >= o) v += u;
+    }
+    if (tid < 27) rp[tid + 1] = v;
+    if (tid == 0) rp[0] = 0;
   }
   __syncthreads();
   const int ncand = rp[27];
-  const int h0 = off_c[2 * cell], h1 = off_c[2 * cell + 2];  // all active particles of the cell
+  const int h0 = hrange[0], h1 = hrange[1];  // all active particles of the cell
   const R L0 = (R)g.L[0], L1 = (R)g.L[1], L2 = (R)g.L[2];
   const R iL0 = (R)(1.0 / g.L[0]), iL1 = (R)(1.0 / g.L[1]), iL2 = (R)(1.0 / g.L[2]);
   const R rc2 = (R)(g.rc * g.rc);
@@ -1082,8 +1124,34 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
     const int hi = tid % nh, grp = tid / nh;
     const bool act = grp < G;
     real4<R> me;
-    if (act) me = part[hb + hi];
+    int iout = 0;
+    R prev[4] = {R(0), R(0), R(0), R(0)};
+    if (act) {
+      me = part[hb + hi];
+      if (grp == 0) {
+        // the outputs this particle adds to, fetched now so their latency
+        // hides behind the pair loop
+        iout = perm[hb + hi];
+        if (out_vec) {
+          prev[0] = out_vec[3 * iout];
+          prev[1] = out_vec[3 * iout + 1];
+          prev[2] = out_vec[3 * iout + 2];
+        }
+        if (out_sca) prev[3] = out_sca[iout];
+      }
+    }
     R fx = 0, fy = 0, fz = 0, ph = 0;
+    // separation to staged candidate k (image already applied where fixed)
+    auto sep = [&](int k, R &ddx, R &ddy, R &ddz) {
+      const real4<R> u = cand[k];
+      ddx = me.x - u.x;
+      ddy = me.y - u.y;
+      ddz = me.z - u.z;
+      if (mi0) ddx -= L0 * rint(ddx * iL0);
+      if (mi1) ddy -= L1 * rint(ddy * iL1);
+      if (mi2) ddz -= L2 * rint(ddz * iL2);
+      return u.w;
+    };
     for (int c0 = 0; c0 < ncand; c0 += kPairChunk) {
       const int nc = min(kPairChunk, ncand - c0);
       __syncthreads();
@@ -1096,24 +1164,39 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
           const int mid = (lo + hi2) >> 1;
           if (rp[mid] <= c) lo = mid; else hi2 = mid;
         }
-        cand[k] = part[rs[lo] + (c - rp[lo])];
+        real4<R> u = part[rs[lo] + (c - rp[lo])];
+        u.x += rsh[lo][0];
+        u.y += rsh[lo][1];
+        u.z += rsh[lo][2];
+        cand[k] = u;
       }
       __syncthreads();
       if (act) {
-        for (int k = grp; k < nc; k += G) {
-          const real4<R> u = cand[k];
-          R ddx = me.x - u.x, ddy = me.y - u.y, ddz = me.z - u.z;
-          ddx -= L0 * rint(ddx * iL0);
-          ddy -= L1 * rint(ddy * iL1);
-          ddz -= L2 * rint(ddz * iL2);
-          const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          if (r2 < rc2 && r2 > R(0)) {
-            const R ir = rsqrt(r2);
+        // pass 1 marks the candidates inside the cutoff in a 32-bit mask;
+        // pass 2 does the erfc/exp work for the marked ones only, so lanes
+        // that miss do not idle through it
+        const int nmine = (nc - grp + G - 1) / G;  // candidates grp, grp+G, ...
+        for (int m0 = 0; m0 < nmine; m0 += 32) {
+          unsigned mask = 0u;
+          const int mend = min(32, nmine - m0);
+          for (int b = 0; b < mend; ++b) {
+            R ddx, ddy, ddz;
+            sep(grp + G * (m0 + b), ddx, ddy, ddz);
+            const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (r2 < rc2 && r2 > R(0)) mask |= 1u << b;
+          }
+          while (mask) {
+            const int b = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            R ddx, ddy, ddz;
+            const R qj = sep(grp + G * (m0 + b), ddx, ddy, ddz);
+            const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const R ir = rsqrt_r(r2);
             const R r = r2 * ir;
             const R ex = exp_fast(-al2 * r2);
             const R ec = erfc_with_exp(al * r, ex) * ir;
-            const R fs = u.w * (ec + c2a * ex) * ir * ir;
-            ph += u.w * ec;
+            const R fs = qj * (ec + c2a * ex) * ir * ir;
+            ph += qj * ec;
             fx += fs * ddx;
             fy += fs * ddy;
             fz += fs * ddz;
@@ -1137,25 +1220,16 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
       }
       const R qi = me.w;
       e += 0.5 * (double)qi * (double)ph;
-      const int i = perm[hb + hi];
+      const int i = iout;
       const double phs = g.ke * (double)ph + c_self * (double)qi + phi_bg;
-      if (MODE == 0) {
-        if (out_vec) {
-          const R c = (R)g.ke * qi;
-          out_vec[3 * i] += c * fx;
-          out_vec[3 * i + 1] += c * fy;
-          out_vec[3 * i + 2] += c * fz;
-        }
-        if (out_sca) out_sca[i] += (R)phs;
-      } else {
-        if (out_vec) {
-          const R c = -gscale * (R)g.ke * qi;
-          out_vec[3 * i] += c * fx;
-          out_vec[3 * i + 1] += c * fy;
-          out_vec[3 * i + 2] += c * fz;
-        }
-        if (out_sca) out_sca[i] += gscale * (R)phs;
+      const R c = MODE == 0 ? (R)g.ke * qi : -gscale * (R)g.ke * qi;
+      const R cs = MODE == 0 ? R(1) : gscale;
+      if (out_vec) {
+        out_vec[3 * i] = prev[0] + c * fx;
+        out_vec[3 * i + 1] = prev[1] + c * fy;
+        out_vec[3 * i + 2] = prev[2] + c * fz;
       }
+      if (out_sca) out_sca[i] = prev[3] + cs * (R)phs;
     }
   }
   if (MODE == 0) {
@@ -1452,8 +1526,12 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   ENUF_TRY(hipGetLastError());
   mark(7);
   // pair
-  hipLaunchKernelGGL((k_pair<R, 0>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                     w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
+  if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
+    hipLaunchKernelGGL((k_pair<R, 0, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
+                       w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
+  else
+    hipLaunchKernelGGL((k_pair<R, 0, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
+                       w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
   ENUF_TRY(hipGetLastError());
   mark(8);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, (const double *)w.kpart,
@@ -1473,8 +1551,12 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
   const R pref = (R)(g.ke * 4.0 * 3.14159265358979323846 / V);
   dispatch_gather<R>(g, w, st, pref, (R)gscale, dEdx, dEdq, true);
   ENUF_TRY(hipGetLastError());
-  hipLaunchKernelGGL((k_pair<R, 1>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                     w.perm_c, w.off_c, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
+  if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
+    hipLaunchKernelGGL((k_pair<R, 1, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
+                       w.perm_c, w.off_c, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
+  else
+    hipLaunchKernelGGL((k_pair<R, 1, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
+                       w.perm_c, w.off_c, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
   return hipGetLastError();
 }
 

@@ -1,0 +1,102 @@
+"""ENUF parameter selection: (alpha, M per axis, p, r_c) for a target RMS
+force error.
+
+Three selectors:
+  heuristic   the paper's relations (Eq. 31-32): fix the target delta and the
+              reciprocal cutoff n_c, take alpha from Eq. 31 and r_c from
+              Eq. 32, and raise n_c until r_c fits a short-range cutoff
+              (Sec. 2.3.2); the grid holds modes up to n_c
+  grid search the fastest setting whose measured error meets the target, from
+              a sweep of the method itself (sweep.py)
+  mlp         a 5 -> 3x64 -> 6 network (mlp.py kernels) trained on those sweeps
+
+Features: (log10 N, Ly/Lx, Lz/Lx, charged fraction, log10 target error).
+Targets:  (alpha a, log2 Mx, log2 My, log2 Mz, p, r_c / a), a = (V/N)^(1/3).
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MODEL_PATH = os.path.join(HERE, "data", "param_mlp.npz")
+P_CHOICES = (4, 6, 8)
+M_MIN, M_MAX = 8, 512
+
+
+def spacing(N, box):
+    return (float(np.prod(box)) / N) ** (1.0 / 3.0)
+
+
+def features(N, box, f_q, target):
+    box = np.asarray(box, float)
+    return np.array([math.log10(N), box[1] / box[0], box[2] / box[0], f_q, math.log10(target)], np.float64)
+
+
+def snap(box, N, alpha_a, log2M, p, rc_a):
+    """Valid setting from continuous predictions: M a power of two in
+    [8, 512] (rounded up), p in {4, 6, 8} with 2p <= M, r_c <= min(L)/2."""
+    box = np.asarray(box, float)
+    a = spacing(N, box)
+    alpha = float(alpha_a) / a
+    M = [int(min(M_MAX, max(M_MIN, 2 ** math.ceil(float(v) - 1e-6)))) for v in log2M]
+    pp = min(P_CHOICES, key=lambda c: abs(c - float(p)))
+    while any(2 * pp > m for m in M):
+        pp -= 2
+    rc = min(float(rc_a) * a, 0.5 * float(box.min()))
+    return {"alpha": alpha, "M": tuple(M), "p": int(pp), "r_c": rc}
+
+
+def heuristic(N, box, f_q, target, rc_max_a=3.0, p=6):
+    """Eq. 31-32: exp(-pi^2 n_c^2/(alpha L)^2) = delta and erfc(alpha r_c) ~
+    exp(-alpha^2 r_c^2) = delta; n_c is raised from 2 until r_c <= the
+    short-range cutoff rc_max_a * a.  The grid keeps modes |n| <= n_c."""
+    box = np.asarray(box, float)
+    a = spacing(N, box)
+    L = float(box[0])
+    s = math.sqrt(-math.log(target))
+    for n_c in range(2, 512):
+        alpha = math.pi * n_c / (L * s)          # Eq. 31 at equality
+        rc = s / alpha                           # Eq. 32 at equality
+        if rc <= min(rc_max_a * a, 0.5 * float(box.min())):
+            break
+    M = [int(min(M_MAX, max(M_MIN, 2 ** math.ceil(math.log2(2 * n_c * box[d] / L + 2))))) for d in range(3)]
+    pp = p
+    while any(2 * pp > m for m in M):
+        pp -= 2
+    return {"alpha": alpha, "M": tuple(M), "p": pp, "r_c": rc}
+
+
+class Predictor:
+    """Trained network plus its feature/target normalisation."""
+
+    def __init__(self, path=MODEL_PATH, device="cuda"):
+        from . import mlp
+
+        d = np.load(path)
+        self.xm, self.xs, self.ym, self.ys = d["x_mean"], d["x_std"], d["y_mean"], d["y_std"]
+        dims = tuple(int(v) for v in d["dims"])
+        self.net = mlp.MLP(*dims, params=d["params"], device=device)
+
+    def predict_raw(self, F):
+        import torch
+
+        Xn = (np.atleast_2d(F) - self.xm) / self.xs
+        Y = self.net.forward(torch.tensor(Xn, dtype=torch.float32)).cpu().numpy().astype(np.float64)
+        return Y * self.ys + self.ym
+
+    def select(self, N, box, f_q, target):
+        y = self.predict_raw(features(N, box, f_q, target))[0]
+        return snap(box, N, y[0], y[1:4], y[4], y[5])
+
+
+def grid_search(sweep_row, target):
+    """Fastest measured setting meeting `target` in one system's sweep record
+    (see sweep.py); None when no setting meets it."""
+    best = None
+    for s in sweep_row["settings"]:
+        if s["err"] <= target and (best is None or s["time"] < best["time"]):
+            best = s
+    return best
