@@ -40,24 +40,26 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(w, rs, nq):
+def algorithmic_bytes(w, rs, nq, nfield=3):
     """Algorithmic HBM bytes of each HBM-bound phase for one evaluation.
 
-    rs = bytes per real; nq = active (charged) particles; G = grid points.
+    rs = bytes per real; nq = active (charged) particles; G = grid points (the
+    half spectrum, Mx/2 x My x Mz complex, is also G reals); nfield = 3 field
+    spectra for forces (E_x, E_y, E_z).
     spread:  read particles (4 reals) + write the grid once
-    fft_fwd: x pass read G reals / write G/2 complex; y pass read+write G/2 complex
-    influence_z: read G/2 complex, write 4 spectra of G/2 complex
-    fft_inv: y passes read+write 4 x G/2 complex; x passes read 4 x G/2 complex,
-             write G x 4 reals
-    gather:  read particles (4 reals) + perm (4 B) + fields (G x 4 reals) and write
-             3 force reals per particle
+    fft_fwd: x pass read G reals / write G; y pass read + write G
+    influence_z: read G, write nfield x G
+    fft_inv: y pass read + write nfield x G; x pass read nfield x G, write the
+             interleaved field array G x 4 reals
+    gather:  read particles (4 reals) + perm (4 B) + fields (G x 4 reals) and
+             write 3 force reals per particle
     """
     G = int(np.prod(w.M))
     return {
         "spread": nq * 4 * rs + G * rs,
-        "fft_fwd": (G * rs + G * rs) + (2 * G * rs),
-        "influence_z": G * rs + 4 * G * rs,
-        "fft_inv": 2 * 4 * G * rs + (4 * G * rs + 4 * G * rs),
+        "fft_fwd": 2 * G * rs + 2 * G * rs,
+        "influence_z": G * rs + nfield * G * rs,
+        "fft_inv": 2 * nfield * G * rs + (nfield * G * rs + 4 * G * rs),
         "gather": nq * (4 * rs + 4 + 3 * rs) + 4 * G * rs,
     }
 
@@ -132,6 +134,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=None, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (5 times): the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures a single GPU: this ENUF build has no multi-GPU path "
@@ -140,6 +145,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe is not None:
+        n = int(args.copy_probe * 2 ** 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}), flush=True)
+        return
 
     from paper_2004_12484_amd import enuf, inputs
 

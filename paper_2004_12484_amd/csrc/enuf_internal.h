@@ -23,6 +23,7 @@ constexpr int kPairBlock = 128;      // threads per cell in the pair kernel
 constexpr int kPairChunk = 512;      // neighbour particles staged in LDS at a time
 constexpr int kScanBlock = 256;      // threads per scan block
 constexpr int kScanChunk = 4 * kScanBlock;  // bins per scan block
+constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)
 
 // Geometry and parameters, passed by value to kernels.
 struct Geom {
@@ -64,7 +65,7 @@ struct Work {
   void *fspec = nullptr;    // complex [4][G/2]
   void *field = nullptr;    // real4 [G]
   void *tables = nullptr;   // twiddles and window transforms (real)
-  size_t tab_off[8] = {0};  // element offsets inside `tables`
+  size_t tab_off[kTabSlots] = {0};  // element offsets inside `tables`
 };
 
 // Launch-configuration numbers the host needs to size partial buffers.
@@ -78,8 +79,8 @@ int nblk_z(const Geom &g, bool fp64);
 
 // Fill the twiddle / window tables on the host (size in reals returned by
 // table_size()).  `host` must hold table_size(g) reals of the precision.
-size_t table_size(const Geom &g, size_t off[8]);
-template <typename R> void fill_tables(const Geom &g, const size_t off[8], R *host);
+size_t table_size(const Geom &g, size_t off[kTabSlots]);
+template <typename R> void fill_tables(const Geom &g, const size_t off[kTabSlots], R *host);
 
 // One forward evaluation: every phase enqueued on `st`.  `ev` (optional) is
 // an array of kPhases+1 events recorded between phases.

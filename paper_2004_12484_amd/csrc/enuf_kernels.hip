@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 
 namespace enuf {
 
@@ -566,255 +567,358 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
 }
 
 // --------------------------------------------------------------------------
-// FFT pencils in LDS: Stockham autosort, radix 4 (and one radix-2 stage for
-// odd powers of two), ping-pong between two LDS buffers.  Element i of pencil
-// f lives at buf[i*nb + f] so neighbouring lanes touch neighbouring words.
-// tw[m] = exp(-2 pi i m / n).  DIR = -1 forward, +1 inverse (unnormalised).
-// Returns the buffer holding the result.
+// FFT pencils.  A pencil of length n = 2^ln is transformed by one to three
+// Stockham autosort stages of radix 16, 8 or 4 whose butterflies keep their
+// RAD inputs in registers: a stage reads and writes each element once.
+// Stage (radix RAD, span Ns = product of the earlier radices): butterfly j,
+// k = j mod Ns, takes elements j + r n/RAD (r < RAD), multiplies element r
+// by exp(DIR 2 pi i r k / (Ns RAD)), applies the RAD-point DFT and writes
+// output r to (j - k) RAD + k + r Ns.  The first stage reads through a
+// caller-supplied loader and the last writes through a storer (global memory
+// or LDS); intermediate stages go through LDS, element i of pencil f of
+// batch o at buf[(o n + i) ld + f] so neighbouring lanes (consecutive f)
+// touch neighbouring words.  tw[m] = exp(-2 pi i m / n).  DIR = -1 forward,
+// +1 inverse (unnormalised).
 // --------------------------------------------------------------------------
+constexpr double kCos16[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+constexpr double kSin16[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                              1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+
+// a * exp(DIR 2 pi i E / 16)
+template <typename R, int DIR, int E>
+__device__ __forceinline__ Cx<R> wmul16(Cx<R> a) {
+  constexpr int e = ((E % 16) + 16) % 16;
+  if constexpr (e == 0) {
+    return a;
+  } else if constexpr (e == 4) {
+    return cmuli<R, DIR>(a);
+  } else if constexpr (e == 8) {
+    return Cx<R>{-a.x, -a.y};
+  } else if constexpr (e == 12) {
+    return cmuli<R, -DIR>(a);
+  } else if constexpr (e > 8) {
+    const Cx<R> b = wmul16<R, DIR, e - 8>(a);
+    return Cx<R>{-b.x, -b.y};
+  } else {
+    const R c = (R)kCos16[e], s = (R)(DIR * kSin16[e]);
+    return Cx<R>{a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
 template <typename R, int DIR>
-__device__ Cx<R> *lds_fft(Cx<R> *a, Cx<R> *b, int n, int nb, const Cx<R> *__restrict__ tw) {
-  Cx<R> *src = a, *dst = b;
-  for (int Ns = 1; Ns < n;) {
-    const int Rdx = ((n / Ns) % 4 == 0) ? 4 : 2;
-    const int nbf = n / Rdx;
-    const int tws = n / (Ns * Rdx);
-    for (int w = threadIdx.x; w < nbf * nb; w += blockDim.x) {
-      const int f = w % nb, j = w / nb;
-      const int k = j & (Ns - 1);
-      const int ob = (j - k) * Rdx + k;
-      if (Rdx == 4) {
-        Cx<R> v0 = src[(j)*nb + f], v1 = src[(j + nbf) * nb + f];
-        Cx<R> v2 = src[(j + 2 * nbf) * nb + f], v3 = src[(j + 3 * nbf) * nb + f];
-        if (Ns > 1) {
-          Cx<R> w1 = tw[k * tws], w2 = tw[2 * k * tws], w3 = tw[3 * k * tws];
-          if (DIR > 0) { w1 = cconj(w1); w2 = cconj(w2); w3 = cconj(w3); }
-          v1 = cmul(v1, w1);
-          v2 = cmul(v2, w2);
-          v3 = cmul(v3, w3);
-        }
-        const Cx<R> s02 = cadd(v0, v2), d02 = csub(v0, v2);
-        const Cx<R> s13 = cadd(v1, v3), d13 = csub(v1, v3);
-        const Cx<R> id13 = cmuli<R, DIR>(d13);
-        dst[(ob)*nb + f] = cadd(s02, s13);
-        dst[(ob + Ns) * nb + f] = cadd(d02, id13);
-        dst[(ob + 2 * Ns) * nb + f] = csub(s02, s13);
-        dst[(ob + 3 * Ns) * nb + f] = csub(d02, id13);
-      } else {
-        Cx<R> v0 = src[(j)*nb + f], v1 = src[(j + nbf) * nb + f];
-        if (Ns > 1) {
-          Cx<R> w1 = tw[k * tws];
-          if (DIR > 0) w1 = cconj(w1);
-          v1 = cmul(v1, w1);
-        }
-        dst[(ob)*nb + f] = cadd(v0, v1);
-        dst[(ob + Ns) * nb + f] = csub(v0, v1);
+__device__ __forceinline__ void dft4(Cx<R> &a0, Cx<R> &a1, Cx<R> &a2, Cx<R> &a3) {
+  const Cx<R> s02 = cadd(a0, a2), d02 = csub(a0, a2), s13 = cadd(a1, a3);
+  const Cx<R> id13 = cmuli<R, DIR>(csub(a1, a3));
+  a0 = cadd(s02, s13);
+  a1 = cadd(d02, id13);
+  a2 = csub(s02, s13);
+  a3 = csub(d02, id13);
+}
+
+// RAD-point DFT in place, natural order in and out
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ void dft(Cx<R> (&v)[RAD]) {
+  if constexpr (RAD == 4) {
+    dft4<R, DIR>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (RAD == 8) {
+    // even / odd halves, then X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k
+    Cx<R> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    Cx<R> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<R, DIR>(e0, e1, e2, e3);
+    dft4<R, DIR>(o0, o1, o2, o3);
+    o1 = wmul16<R, DIR, 2>(o1);
+    o2 = wmul16<R, DIR, 4>(o2);
+    o3 = wmul16<R, DIR, 6>(o3);
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+  } else {
+    static_assert(RAD == 16, "radix 4, 8 or 16");
+    // 4 x 4: index n = n2 + 4 n1, k = k1 + 4 k2.  Columns (fixed n2) first,
+    // twiddle W16^(n2 k1), then rows (fixed k1); row k1 output k2 is X_{k1+4k2}.
+    dft4<R, DIR>(v[0], v[4], v[8], v[12]);
+    dft4<R, DIR>(v[1], v[5], v[9], v[13]);
+    dft4<R, DIR>(v[2], v[6], v[10], v[14]);
+    dft4<R, DIR>(v[3], v[7], v[11], v[15]);
+    v[5] = wmul16<R, DIR, 1>(v[5]);
+    v[9] = wmul16<R, DIR, 2>(v[9]);
+    v[13] = wmul16<R, DIR, 3>(v[13]);
+    v[6] = wmul16<R, DIR, 2>(v[6]);
+    v[10] = wmul16<R, DIR, 4>(v[10]);
+    v[14] = wmul16<R, DIR, 6>(v[14]);
+    v[7] = wmul16<R, DIR, 3>(v[7]);
+    v[11] = wmul16<R, DIR, 6>(v[11]);
+    v[15] = wmul16<R, DIR, 9>(v[15]);
+    Cx<R> t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      Cx<R> a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+      dft4<R, DIR>(a0, a1, a2, a3);
+      t[k1] = a0;
+      t[k1 + 4] = a1;
+      t[k1 + 8] = a2;
+      t[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = t[i];
+  }
+}
+
+template <typename R, int RAD, int DIR, class LD, class ST>
+__device__ __forceinline__ void fft_stage(int ln, int lns, int lnb, int nrep, const Cx<R> *__restrict__ tw, LD ld,
+                                          ST st) {
+  constexpr int LR = RAD == 16 ? 4 : (RAD == 8 ? 3 : 2);
+  const int lq = ln - LR;  // log2 of butterflies per pencil
+  const int lt = ln - lns - LR;
+  const int total = nrep << (lq + lnb);
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int f = w & ((1 << lnb) - 1);
+    const int t = w >> lnb;
+    const int j = t & ((1 << lq) - 1);
+    const int o = t >> lq;
+    const int k = j & ((1 << lns) - 1);
+    Cx<R> v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = ld(o, j + (r << lq), f);
+    if (lns > 0) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        Cx<R> wr = tw[(r * k) << lt];
+        if (DIR > 0) wr = cconj(wr);
+        v[r] = cmul(v[r], wr);
       }
     }
-    __syncthreads();
-    Cx<R> *tmp = src;
-    src = dst;
-    dst = tmp;
-    Ns *= Rdx;
+    dft<R, RAD, DIR>(v);
+    const int ob = ((j - k) << LR) + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) st(o, ob + (r << lns), f, v[r]);
   }
-  return src;
+}
+
+__host__ __device__ constexpr int fft_nstages(int ln) { return ln <= 4 ? 1 : (ln <= 8 ? 2 : 3); }
+
+// Runs the stages for length 2^ln (ln in 2..10) over nrep batches of 2^lnb
+// pencils.  Stage 0 reads through `first`, the last stage writes through
+// `last`; stage 0 / stage 1 outputs (when not last) go to LDS X / Y with
+// pencil stride ldp.  Barriers separate the stages; the caller synchronises
+// before the first and after the last.
+template <typename R, int DIR, class LD, class ST>
+__device__ void fft_run(int ln, int lnb, int nrep, const Cx<R> *__restrict__ tw, Cx<R> *X, Cx<R> *Y, int ldp,
+                        LD first, ST last) {
+  auto ldX = [=](int o, int i, int f) { return X[((o << ln) + i) * ldp + f]; };
+  auto stX = [=](int o, int i, int f, Cx<R> v) { X[((o << ln) + i) * ldp + f] = v; };
+  auto ldY = [=](int o, int i, int f) { return Y[((o << ln) + i) * ldp + f]; };
+  auto stY = [=](int o, int i, int f, Cx<R> v) { Y[((o << ln) + i) * ldp + f] = v; };
+  switch (ln) {
+    case 2: fft_stage<R, 4, DIR>(ln, 0, lnb, nrep, tw, first, last); break;
+    case 3: fft_stage<R, 8, DIR>(ln, 0, lnb, nrep, tw, first, last); break;
+    case 4: fft_stage<R, 16, DIR>(ln, 0, lnb, nrep, tw, first, last); break;
+    case 5:
+      fft_stage<R, 8, DIR>(ln, 0, lnb, nrep, tw, first, stX);
+      __syncthreads();
+      fft_stage<R, 4, DIR>(ln, 3, lnb, nrep, tw, ldX, last);
+      break;
+    case 6:
+      fft_stage<R, 8, DIR>(ln, 0, lnb, nrep, tw, first, stX);
+      __syncthreads();
+      fft_stage<R, 8, DIR>(ln, 3, lnb, nrep, tw, ldX, last);
+      break;
+    case 7:
+      fft_stage<R, 16, DIR>(ln, 0, lnb, nrep, tw, first, stX);
+      __syncthreads();
+      fft_stage<R, 8, DIR>(ln, 4, lnb, nrep, tw, ldX, last);
+      break;
+    case 8:
+      fft_stage<R, 16, DIR>(ln, 0, lnb, nrep, tw, first, stX);
+      __syncthreads();
+      fft_stage<R, 16, DIR>(ln, 4, lnb, nrep, tw, ldX, last);
+      break;
+    case 9:
+      fft_stage<R, 8, DIR>(ln, 0, lnb, nrep, tw, first, stX);
+      __syncthreads();
+      fft_stage<R, 8, DIR>(ln, 3, lnb, nrep, tw, ldX, stY);
+      __syncthreads();
+      fft_stage<R, 8, DIR>(ln, 6, lnb, nrep, tw, ldY, last);
+      break;
+    default:
+      fft_stage<R, 16, DIR>(ln, 0, lnb, nrep, tw, first, stX);
+      __syncthreads();
+      fft_stage<R, 8, DIR>(ln, 4, lnb, nrep, tw, ldX, stY);
+      __syncthreads();
+      fft_stage<R, 8, DIR>(ln, 7, lnb, nrep, tw, ldY, last);
+      break;
+  }
 }
 
 // x pass, forward: each row of Mx reals -> bins 0 .. Mx/2-1 (the Nyquist bin
 // is not kept: those modes are outside the k-set).  The row is packed as
 // z_j = x_{2j} + i x_{2j+1}, transformed at length n = Mx/2 and untangled:
 // X_k = (Z_k + conj Z_{n-k})/2 - (i/2) e^{-2 pi i k/Mx} (Z_k - conj Z_{n-k}).
+// A block takes 2^lnb rows; LDS pencil stride ldp (odd when > 1) keeps the
+// row <-> pencil transposes free of bank conflicts.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(const R *__restrict__ grid, Cx<R> *__restrict__ spec,
-                                                      Geom g, const Cx<R> *__restrict__ tw_n,
-                                                      const Cx<R> *__restrict__ tw_2n, int nb) {
+                                                      int lnh, int lnb, const Cx<R> *__restrict__ tw_n,
+                                                      const Cx<R> *__restrict__ tw_2n) {
   extern __shared__ unsigned char smem_raw[];
-  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
-  const int n = g.M[0] / 2;
-  Cx<R> *B = A + n * nb;
+  const int n = 1 << lnh, nb = 1 << lnb;
+  const int ldp = nb == 1 ? 1 : nb + 1;
+  Cx<R> *B0 = reinterpret_cast<Cx<R> *>(smem_raw);
+  Cx<R> *B1 = B0 + n * ldp;
   const size_t row0 = (size_t)blockIdx.x * nb;
-  const Cx<R> *src = reinterpret_cast<const Cx<R> *>(grid) + row0 * n;
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int f = e / n, i = e % n;
-    A[i * nb + f] = src[(size_t)f * n + i];
-  }
+  const Cx<R> *src = reinterpret_cast<const Cx<R> *>(grid) + (row0 << lnh);
+  for (int e = threadIdx.x; e < (n << lnb); e += blockDim.x) B0[(e & (n - 1)) * ldp + (e >> lnh)] = src[e];
   __syncthreads();
-  Cx<R> *Z = lds_fft<R, -1>(A, B, n, nb, tw_n);
-  Cx<R> *dst = spec + row0 * n;
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int f = e / n, k = e % n;
-    const Cx<R> zk = Z[k * nb + f];
-    const Cx<R> zm = cconj(Z[((n - k) & (n - 1)) * nb + f]);
+  Cx<R> *res = (fft_nstages(lnh) & 1) ? B1 : B0;
+  fft_run<R, -1>(lnh, lnb, 1, tw_n, B1, B0, ldp, [=](int, int i, int f) { return B0[i * ldp + f]; },
+                 [=](int, int i, int f, Cx<R> v) { res[i * ldp + f] = v; });
+  __syncthreads();
+  Cx<R> *dst = spec + (row0 << lnh);
+  for (int e = threadIdx.x; e < (n << lnb); e += blockDim.x) {
+    const int f = e >> lnh, k = e & (n - 1);
+    const Cx<R> zk = res[k * ldp + f];
+    const Cx<R> zm = cconj(res[((n - k) & (n - 1)) * ldp + f]);
     const Cx<R> s = cadd(zk, zm), d = csub(zk, zm);
     const Cx<R> wd = cmul(tw_2n[k], d);
     // X = s/2 - (i/2) w d
-    dst[(size_t)f * n + k] = Cx<R>{R(0.5) * (s.x + wd.y), R(0.5) * (s.y - wd.x)};
+    dst[e] = Cx<R>{R(0.5) * (s.x + wd.y), R(0.5) * (s.y - wd.x)};
   }
 }
 
-// Complex pencils along an axis of length n with element stride `inner`
-// (the contiguous dimension); a block takes nb consecutive pencils.
-// blockIdx.x: pencil block, blockIdx.y: outer index, blockIdx.z: component.
+// Complex pencils along y (length 2^ln, element stride 2^linner: x is the
+// contiguous dimension), in place; a block takes 2^lnb consecutive pencils.
+// blockIdx.x: pencil block, blockIdx.y: z plane, blockIdx.z: component.
 template <typename R, int DIR>
-__global__ __launch_bounds__(kBlock) void k_fft_axis(Cx<R> *data, int n, int inner, size_t outer_stride,
-                                                     size_t comp_stride, const Cx<R> *__restrict__ tw,
-                                                     int nb) {
+__global__ __launch_bounds__(kBlock) void k_fft_y(Cx<R> *data, int ln, int linner, size_t plane_stride,
+                                                  size_t comp_stride, const Cx<R> *__restrict__ tw, int lnb) {
   extern __shared__ unsigned char smem_raw[];
-  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
-  Cx<R> *B = A + n * nb;
-  Cx<R> *base = data + blockIdx.z * comp_stride + blockIdx.y * outer_stride + (size_t)blockIdx.x * nb;
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int f = e % nb, i = e / nb;
-    A[e] = base[(size_t)i * inner + f];
-  }
-  __syncthreads();
-  Cx<R> *res = lds_fft<R, DIR>(A, B, n, nb, tw);
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int f = e % nb, i = e / nb;
-    base[(size_t)i * inner + f] = res[e];
-  }
+  const int nb = 1 << lnb;
+  Cx<R> *X = reinterpret_cast<Cx<R> *>(smem_raw);
+  Cx<R> *Y = X + (nb << ln);
+  Cx<R> *base = data + blockIdx.z * comp_stride + blockIdx.y * plane_stride + ((size_t)blockIdx.x << lnb);
+  fft_run<R, DIR>(ln, lnb, 1, tw, X, Y, nb, [=](int, int i, int f) { return base[((size_t)i << linner) + f]; },
+                  [=](int, int i, int f, Cx<R> v) { base[((size_t)i << linner) + f] = v; });
 }
 
 // z pass fused with the scaling and influence steps.  For each pencil
 // (kx, ky): forward transform along z; then for every mode n in the k-set
 //   g(n) = A(k) / c(n)^2,  A = exp(-k^2/4a^2)/k^2,  c = window transform,
+// which factorises as s_x(kx) s_y(ky) s_z(kz) / k^2 with
+// s_d = exp(-k_d^2/4a^2) / c_d^2 (zero at the Nyquist index);
 // energy += w_x g |rho^|^2 (w_x = 2 for kx > 0: the mirrored half),
 // field spectra E^_d = -i k_d g rho^ (d = x,y,z) and psi^ = g rho^, each
-// transformed back along z and written to fspec[d].
+// transformed back along z and written to fspec[d].  The nf field pencils
+// are transformed as one batch of nfp (nf or 1) at a time.
+// tab: s_x (Mx/2), s_y (My), s_z (Mz), k_x (Mx/2), k_y (My), k_z (Mz).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec,
-                                                    Geom g, const Cx<R> *__restrict__ tw_z,
-                                                    const R *__restrict__ cwx, const R *__restrict__ cwy,
-                                                    const R *__restrict__ cwz, double *kpart, int nb,
-                                                    int nfield) {
+                                                    Geom g, int lnz, int lhx, int lnb, int nf, int nfp,
+                                                    const Cx<R> *__restrict__ tw_z, const R *__restrict__ sx,
+                                                    const R *__restrict__ sy, const R *__restrict__ sz,
+                                                    const R *__restrict__ kvx, const R *__restrict__ kvy,
+                                                    const R *__restrict__ kvz, double *kpart) {
   extern __shared__ unsigned char smem_raw[];
-  const int n = g.M[2];
-  const int hx = g.M[0] / 2;
-  const int inner = hx * g.M[1];
-  const size_t half = (size_t)inner * n;
-  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
-  Cx<R> *B = A + n * nb;
-  Cx<R> *C = B + n * nb;
-  R *gk = reinterpret_cast<R *>(C + n * nb);
-  const int p0 = blockIdx.x * nb;
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int f = e % nb, i = e / nb;
-    A[e] = spec[(size_t)i * inner + p0 + f];
-  }
+  const int n = 1 << lnz, nb = 1 << lnb, hx = 1 << lhx;
+  const size_t inner = (size_t)hx * g.M[1];
+  const size_t half = inner << lnz;
+  const int nst = fft_nstages(lnz);
+  Cx<R> *S = reinterpret_cast<Cx<R> *>(smem_raw);  // n x nb, the (scaled) spectrum
+  Cx<R> *X = S + (n << lnb);                        // nfp x n x nb when nst >= 2
+  Cx<R> *Y = X + (nst >= 2 ? (nfp << (lnz + lnb)) : 0);
+  const size_t p0 = (size_t)blockIdx.x << lnb;
+  fft_run<R, -1>(lnz, lnb, 1, tw_z, X, Y, nb, [=](int, int i, int f) { return spec[i * inner + p0 + f]; },
+                 [=](int, int i, int f, Cx<R> v) { S[i * nb + f] = v; });
   __syncthreads();
-  Cx<R> *S = lds_fft<R, -1>(A, B, n, nb, tw_z);
-  Cx<R> *P0 = (S == A) ? B : A;
-  Cx<R> *P1 = C;
-  const double twopi = 6.283185307179586476925286766559;
-  const double a4 = 1.0 / (4.0 * g.alpha * g.alpha);
   double en = 0.0;
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int f = e % nb, kz = e / nb;
-    const int pidx = p0 + f;
-    const int kx = pidx % hx, ky = pidx / hx;
-    const int ny = ky < g.M[1] / 2 ? ky : ky - g.M[1];
-    const int nz = kz < n / 2 ? kz : kz - n;
-    const bool inK = (ky != g.M[1] / 2) && (kz != n / 2) && !(kx == 0 && ky == 0 && kz == 0);
-    R gv = R(0);
-    if (inK) {
-      const double kxv = twopi * kx / g.L[0], kyv = twopi * ny / g.L[1], kzv = twopi * nz / g.L[2];
-      const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
-      const R c = cwx[kx] * cwy[ky] * cwz[kz];
-      const R A_ = (R)(exp(-k2 * a4) / k2);
-      gv = A_ / (c * c);
-    }
-    gk[e] = gv;
+  for (int e = threadIdx.x; e < (n << lnb); e += blockDim.x) {
+    const int f = e & (nb - 1), kz = e >> lnb;
+    const int pidx = (int)p0 + f;
+    const int kx = pidx & (hx - 1), ky = pidx >> lhx;
+    const R k2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky] + kvz[kz] * kvz[kz];
+    const R gv = k2 > R(0) ? sx[kx] * sy[ky] * sz[kz] / k2 : R(0);
     const Cx<R> r = S[e];
     en += (kx > 0 ? 2.0 : 1.0) * (double)gv * ((double)r.x * r.x + (double)r.y * r.y);
+    S[e] = Cx<R>{gv * r.x, gv * r.y};
   }
   __syncthreads();
-  for (int o = 0; o < nfield; ++o) {
-    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-      const int f = e % nb, kz = e / nb;
-      const Cx<R> r = S[e];
-      const R gv = gk[e];
-      Cx<R> out;
-      if (o < 3) {
-        const int pidx = p0 + f;
-        const int kx = pidx % hx, ky = pidx / hx;
-        int nd;
-        double Ld;
-        if (o == 0) { nd = kx; Ld = g.L[0]; }
-        else if (o == 1) { nd = ky < g.M[1] / 2 ? ky : ky - g.M[1]; Ld = g.L[1]; }
-        else { nd = kz < n / 2 ? kz : kz - n; Ld = g.L[2]; }
-        const R kd = (R)(twopi * nd / Ld) * gv;
-        // -i * kd * r
-        out = Cx<R>{kd * r.y, -kd * r.x};
-      } else {
-        out = Cx<R>{gv * r.x, gv * r.y};
-      }
-      P0[e] = out;
-    }
-    __syncthreads();
-    Cx<R> *res = lds_fft<R, 1>(P0, P1, n, nb, tw_z);
-    Cx<R> *dst = fspec + o * half;
-    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-      const int f = e % nb, i = e / nb;
-      dst[(size_t)i * inner + p0 + f] = res[e];
-    }
+  for (int o0 = 0; o0 < nf; o0 += nfp) {
+    fft_run<R, 1>(
+        lnz, lnb, nfp, tw_z, X, Y, nb,
+        [=](int o, int i, int f) {
+          const Cx<R> v = S[i * nb + f];
+          const int c = o0 + o;
+          if (c == 3) return v;
+          const int pidx = (int)p0 + f;
+          const R kd = c == 0 ? kvx[pidx & (hx - 1)] : (c == 1 ? kvy[pidx >> lhx] : kvz[i]);
+          return Cx<R>{kd * v.y, -kd * v.x};  // -i k_d v
+        },
+        [=](int o, int i, int f, Cx<R> v) { fspec[(o0 + o) * half + i * inner + p0 + f] = v; });
     __syncthreads();
   }
   const double tot = block_sum(en);
   if (threadIdx.x == 0) kpart[blockIdx.x] = tot;
 }
 
-// x pass, inverse, four components: bins 0 .. Mx/2-1 of each field (Nyquist
+// x pass, inverse, nf components: bins 0 .. Mx/2-1 of each field (Nyquist
 // bin zero) -> Mx reals, written interleaved as real4 (E_x, E_y, E_z, psi).
 // Z_k = (X_k + conj X_{n-k}) + i e^{+2 pi i k/Mx} (X_k - conj X_{n-k}),
 // z = inverse transform (length n), x_{2j} = Re z_j, x_{2j+1} = Im z_j.
+// The untangling is folded into the first stage's loads.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__ fspec, real4<R> *__restrict__ field,
-                                                       Geom g, const Cx<R> *__restrict__ tw_n,
-                                                       const Cx<R> *__restrict__ tw_2n, int nb, int nfield) {
+                                                       Geom g, int lnh, int lnb, int nf,
+                                                       const Cx<R> *__restrict__ tw_n,
+                                                       const Cx<R> *__restrict__ tw_2n) {
   extern __shared__ unsigned char smem_raw[];
-  const int n = g.M[0] / 2, Mx = g.M[0];
-  const size_t half = (size_t)n * g.M[1] * g.M[2];
-  Cx<R> *A = reinterpret_cast<Cx<R> *>(smem_raw);
-  Cx<R> *B = A + n * nb;
-  R *out = reinterpret_cast<R *>(B + n * nb);  // [nb][Mx][4]
+  const int n = 1 << lnh, nb = 1 << lnb, Mx = 2 * n;
+  const int ldp = nb == 1 ? 1 : nb + 1;
+  const size_t half = ((size_t)g.M[1] * g.M[2]) << lnh;
+  Cx<R> *B0 = reinterpret_cast<Cx<R> *>(smem_raw);
+  Cx<R> *B1 = B0 + nf * n * ldp;
   const size_t row0 = (size_t)blockIdx.x * nb;
-  for (int o = 0; o < nfield; ++o) {
-    const Cx<R> *src = fspec + o * half + row0 * n;
-    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-      const int f = e / n, k = e % n;
-      A[k * nb + f] = src[(size_t)f * n + k];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-      const int f = e % nb, k = e / nb;
-      const Cx<R> xk = A[k * nb + f];
-      const Cx<R> xm = (k == 0) ? Cx<R>{R(0), R(0)} : cconj(A[(n - k) * nb + f]);
-      const Cx<R> s = cadd(xk, xm), d = csub(xk, xm);
-      const Cx<R> wd = cmul(cconj(tw_2n[k]), d);
-      // s + i * wd
-      B[e] = Cx<R>{s.x - wd.y, s.y + wd.x};
-    }
-    __syncthreads();
-    Cx<R> *z = lds_fft<R, 1>(B, A, n, nb, tw_n);
-    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-      const int f = e % nb, j = e / nb;
-      const Cx<R> v = z[e];
-      out[((size_t)f * Mx + 2 * j) * 4 + o] = v.x;
-      out[((size_t)f * Mx + 2 * j + 1) * 4 + o] = v.y;
-    }
-    __syncthreads();
+  for (int e = threadIdx.x; e < ((nf * n) << lnb); e += blockDim.x) {
+    const int k = e & (n - 1), t = e >> lnh;
+    const int f = t & (nb - 1), o = t >> lnb;
+    B0[(o * n + k) * ldp + f] = fspec[o * half + ((row0 + f) << lnh) + k];
   }
+  __syncthreads();
+  Cx<R> *res = (fft_nstages(lnh) & 1) ? B1 : B0;
+  fft_run<R, 1>(
+      lnh, lnb, nf, tw_n, B1, B0, ldp,
+      [=](int o, int k, int f) {
+        const Cx<R> xk = B0[(o * n + k) * ldp + f];
+        const Cx<R> xm = k == 0 ? Cx<R>{R(0), R(0)} : cconj(B0[(o * n + n - k) * ldp + f]);
+        const Cx<R> s = cadd(xk, xm), d = csub(xk, xm);
+        const Cx<R> wd = cmul(cconj(tw_2n[k]), d);
+        return Cx<R>{s.x - wd.y, s.y + wd.x};  // s + i wd
+      },
+      [=](int o, int i, int f, Cx<R> v) { res[(o * n + i) * ldp + f] = v; });
+  __syncthreads();
   real4<R> *dst = field + row0 * Mx;
-  for (int e = threadIdx.x; e < nb * Mx; e += blockDim.x) {
+  for (int e = threadIdx.x; e < (nb * Mx); e += blockDim.x) {
+    const int xi = e & (Mx - 1), f = e >> (lnh + 1);
+    const int j = xi >> 1;
+    const bool odd = xi & 1;
+    R c[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      if (o < nf) {
+        const Cx<R> v = res[(o * n + j) * ldp + f];
+        c[o] = odd ? v.y : v.x;
+      } else {
+        c[o] = R(0);
+      }
+    }
     real4<R> v;
-    v.x = out[4 * e];
-    v.y = out[4 * e + 1];
-    v.z = out[4 * e + 2];
-    v.w = nfield == 4 ? out[4 * e + 3] : R(0);
+    v.x = c[0];
+    v.y = c[1];
+    v.z = c[2];
+    v.w = c[3];
     dst[e] = v;
   }
 }
-
 // --------------------------------------------------------------------------
 // gather: type-2 interpolation of the four fields (Eq. 35, 42), one thread per
 // active particle in tile order; results scattered to the caller's order.
@@ -1315,47 +1419,86 @@ int build_runs(const Geom &g, int *out) {
   return n;
 }
 
-// pencils per block for a pass so that `per_pencil` bytes * nb <= budget,
-// nb a power of two dividing `count`, at most 16
-static int pick_nb(size_t per_pencil, size_t budget, int count) {
-  int nb = 16;
-  while (nb > 1 && ((size_t)nb * per_pencil > budget || count % nb != 0)) nb >>= 1;
-  return nb;
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
 }
 
-static int nb_xr2c(const Geom &g, size_t cs) { return pick_nb(2 * (g.M[0] / 2) * cs, 32768, g.M[1] * g.M[2]); }
-static int nb_axis(int n, int inner, size_t cs) { return pick_nb(2 * (size_t)n * cs, 32768, inner); }
-static int nb_z(const Geom &g, size_t cs) {
-  return pick_nb((size_t)g.M[2] * (3 * cs + cs / 2), 61440, (g.M[0] / 2) * g.M[1]);
-}
-static int nb_xc2r(const Geom &g, size_t cs) {
-  const int n = g.M[0] / 2;
-  return pick_nb((size_t)n * (2 * cs) + (size_t)g.M[0] * 4 * (cs / 2), 49152, g.M[1] * g.M[2]);
+// Launch shape of the FFT passes: log2 pencils per block and dynamic LDS
+// bytes, the largest batch (at most 16 pencils) that fits the LDS budget and
+// divides the pencil count.
+struct FftPlan {
+  int lnh, lny, lnz, lhx;
+  int lb_r2c, lb_y, lb_z, lb_c2r;
+  int nfp;  // field pencils per inverse-z batch
+  size_t lds_r2c, lds_y, lds_z, lds_c2r;
+  int zblocks;
+};
+
+static size_t pad_ld(int lb) { return lb == 0 ? 1 : (1u << lb) + 1; }
+
+static FftPlan fft_plan(const Geom &g, size_t cs, int nf) {
+  FftPlan P;
+  P.lnh = ilog2(g.M[0] / 2);
+  P.lny = ilog2(g.M[1]);
+  P.lnz = ilog2(g.M[2]);
+  P.lhx = P.lnh;
+  const size_t nh = (size_t)1 << P.lnh, ny = g.M[1], nz = g.M[2];
+  auto pick = [](int count, auto lds_of, size_t budget) {
+    int lb = 4;
+    while (lb > 0 && (lds_of(lb) > budget || count % (1 << lb) != 0)) --lb;
+    return lb;
+  };
+  auto r2c = [&](int lb) { return 2 * nh * pad_ld(lb) * cs; };
+  P.lb_r2c = pick(g.M[1] * g.M[2], r2c, 32768);
+  P.lds_r2c = r2c(P.lb_r2c);
+  const int sty = fft_nstages(P.lny);
+  auto yl = [&](int lb) { return (size_t)((sty >= 2) + (sty == 3)) * ny * ((size_t)1 << lb) * cs; };
+  P.lb_y = pick((int)nh, yl, 32768);
+  P.lds_y = yl(P.lb_y);
+  const int stz = fft_nstages(P.lnz);
+  auto zl = [&](int nfp, int lb) {
+    return (size_t)(1 + (stz >= 2) * nfp + (stz == 3) * nfp) * nz * ((size_t)1 << lb) * cs;
+  };
+  const int zp = (int)nh * g.M[1];
+  P.nfp = nf;
+  P.lb_z = pick(zp, [&](int lb) { return zl(nf, lb); }, 49152);
+  if (zl(nf, P.lb_z) > 49152 || (P.lb_z < 2 && zp >= 4)) {
+    P.nfp = 1;
+    P.lb_z = pick(zp, [&](int lb) { return zl(1, lb); }, 65536);
+  }
+  P.lds_z = zl(P.nfp, P.lb_z);
+  P.zblocks = zp >> P.lb_z;
+  auto c2r = [&](int lb) { return 2 * (size_t)nf * nh * pad_ld(lb) * cs; };
+  P.lb_c2r = pick(g.M[1] * g.M[2], c2r, 32768);
+  P.lds_c2r = c2r(P.lb_c2r);
+  return P;
 }
 
 int nblk_z(const Geom &g, bool fp64) {
   const size_t cs = fp64 ? 16 : 8;
-  return (g.M[0] / 2) * g.M[1] / nb_z(g, cs);
+  return std::max(fft_plan(g, cs, 3).zblocks, fft_plan(g, cs, 4).zblocks);
 }
 
 // table layout (in reals): [0] tw x-half (n=Mx/2) complex, [1] tw e^{-2pi i k/Mx}
-// k<Mx/2 complex, [2] tw y complex, [3] tw z complex, [4] c_x (Mx/2 reals),
-// [5] c_y (My), [6] c_z (Mz)
-size_t table_size(const Geom &g, size_t off[8]) {
+// k<Mx/2 complex, [2] tw y complex, [3] tw z complex, [4..6] influence
+// factors s_x (Mx/2), s_y (My), s_z (Mz), [7..9] wave numbers k_x, k_y, k_z
+size_t table_size(const Geom &g, size_t off[kTabSlots]) {
+  const size_t hx = g.M[0] / 2;
+  const size_t len[kTabSlots - 1] = {2 * hx, 2 * hx, 2 * (size_t)g.M[1], 2 * (size_t)g.M[2], hx,
+                                     (size_t)g.M[1], (size_t)g.M[2], hx, (size_t)g.M[1], (size_t)g.M[2]};
   size_t o = 0;
-  off[0] = o; o += 2 * (g.M[0] / 2);
-  off[1] = o; o += 2 * (g.M[0] / 2);
-  off[2] = o; o += 2 * g.M[1];
-  off[3] = o; o += 2 * g.M[2];
-  off[4] = o; o += g.M[0] / 2;
-  off[5] = o; o += g.M[1];
-  off[6] = o; o += g.M[2];
-  off[7] = o;
+  for (int i = 0; i < kTabSlots - 1; ++i) {
+    off[i] = o;
+    o += len[i];
+  }
+  off[kTabSlots - 1] = o;
   return o;
 }
 
 template <typename R>
-void fill_tables(const Geom &g, const size_t off[8], R *h) {
+void fill_tables(const Geom &g, const size_t off[kTabSlots], R *h) {
   const double pi = 3.14159265358979323846;
   auto tw = [&](R *dst, int n, int period) {
     for (int m = 0; m < n; ++m) {
@@ -1368,21 +1511,26 @@ void fill_tables(const Geom &g, const size_t off[8], R *h) {
   tw(h + off[1], g.M[0] / 2, g.M[0]);
   tw(h + off[2], g.M[1], g.M[1]);
   tw(h + off[3], g.M[2], g.M[2]);
-  // window transform sinc^p(pi n / M), n signed
-  auto cw = [&](R *dst, int cnt, int M) {
+  // per axis: s_d = exp(-k_d^2 / 4 alpha^2) / c_d^2 with the window transform
+  // c_d = sinc^p(pi n / M_d) (n signed; zero at the Nyquist index, which is
+  // outside the k-set), and k_d = 2 pi n / L_d
+  auto axis = [&](R *s, R *kv, int cnt, int d) {
+    const int M = g.M[d];
     for (int k = 0; k < cnt; ++k) {
       const int nn = k < M / 2 ? k : k - M;
       const double t = pi * (double)nn / (double)M;
-      const double s = nn == 0 ? 1.0 : std::sin(t) / t;
-      dst[k] = (R)std::pow(s, g.p);
+      const double c = std::pow(nn == 0 ? 1.0 : std::sin(t) / t, g.p);
+      const double kd = 2.0 * pi * (double)nn / g.L[d];
+      s[k] = (k == M / 2) ? R(0) : (R)(std::exp(-kd * kd / (4.0 * g.alpha * g.alpha)) / (c * c));
+      kv[k] = (R)kd;
     }
   };
-  cw(h + off[4], g.M[0] / 2, g.M[0]);
-  cw(h + off[5], g.M[1], g.M[1]);
-  cw(h + off[6], g.M[2], g.M[2]);
+  axis(h + off[4], h + off[7], g.M[0] / 2, 0);
+  axis(h + off[5], h + off[8], g.M[1], 1);
+  axis(h + off[6], h + off[9], g.M[2], 2);
 }
-template void fill_tables<float>(const Geom &, const size_t[8], float *);
-template void fill_tables<double>(const Geom &, const size_t[8], double *);
+template void fill_tables<float>(const Geom &, const size_t[kTabSlots], float *);
+template void fill_tables<double>(const Geom &, const size_t[kTabSlots], double *);
 
 #define ENUF_TRY(x)                   \
   do {                                \
@@ -1451,12 +1599,14 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   const Cx<R> *tw_x2 = (const Cx<R> *)(tab + w.tab_off[1]);
   const Cx<R> *tw_y = (const Cx<R> *)(tab + w.tab_off[2]);
   const Cx<R> *tw_z = (const Cx<R> *)(tab + w.tab_off[3]);
-  const R *cwx = tab + w.tab_off[4], *cwy = tab + w.tab_off[5], *cwz = tab + w.tab_off[6];
+  const R *sx = tab + w.tab_off[4], *sy = tab + w.tab_off[5], *sz = tab + w.tab_off[6];
+  const R *kvx = tab + w.tab_off[7], *kvy = tab + w.tab_off[8], *kvz = tab + w.tab_off[9];
   const int hx = g.M[0] / 2;
   const size_t halfG = (size_t)hx * g.M[1] * g.M[2];
   // the potential field psi is transformed only when potentials (or a later
   // adjoint) need it; forces use the three ik fields
   const int nfield = want_psi ? 4 : 3;
+  const FftPlan P = fft_plan(g, cs, nfield);
   auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
 
   mark(0);
@@ -1488,35 +1638,23 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   ENUF_TRY(hipGetLastError());
   mark(3);
   // forward x (r2c), y
-  {
-    const int nb = nb_xr2c(g, cs);
-    hipLaunchKernelGGL((k_fft_x_r2c<R>), dim3(g.M[1] * g.M[2] / nb), dim3(kBlock), 2 * hx * nb * cs, st,
-                       (const R *)w.grid, (Cx<R> *)w.spec, g, tw_xh, tw_x2, nb);
-    const int nby = nb_axis(g.M[1], hx, cs);
-    hipLaunchKernelGGL((k_fft_axis<R, -1>), dim3(hx / nby, g.M[2], 1), dim3(kBlock), 2 * g.M[1] * nby * cs,
-                       st, (Cx<R> *)w.spec, g.M[1], hx, (size_t)hx * g.M[1], (size_t)0, tw_y, nby);
-  }
+  hipLaunchKernelGGL((k_fft_x_r2c<R>), dim3((g.M[1] * g.M[2]) >> P.lb_r2c), dim3(kBlock), P.lds_r2c, st,
+                     (const R *)w.grid, (Cx<R> *)w.spec, P.lnh, P.lb_r2c, tw_xh, tw_x2);
+  hipLaunchKernelGGL((k_fft_y<R, -1>), dim3(hx >> P.lb_y, g.M[2], 1), dim3(kBlock), P.lds_y, st,
+                     (Cx<R> *)w.spec, P.lny, P.lhx, (size_t)hx * g.M[1], (size_t)0, tw_y, P.lb_y);
   ENUF_TRY(hipGetLastError());
   mark(4);
-  // z fused: forward z, influence, energy, four inverse z
-  {
-    const int nb = nb_z(g, cs);
-    const size_t sh = (size_t)g.M[2] * nb * (3 * cs + sizeof(R));
-    hipLaunchKernelGGL((k_z_fused<R>), dim3(hx * g.M[1] / nb), dim3(kBlock), sh, st,
-                       (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, tw_z, cwx, cwy, cwz, w.kpart, nb, nfield);
-  }
+  // z fused: forward z, influence, energy, inverse z of the field spectra
+  hipLaunchKernelGGL((k_z_fused<R>), dim3(P.zblocks), dim3(kBlock), P.lds_z, st, (const Cx<R> *)w.spec,
+                     (Cx<R> *)w.fspec, g, P.lnz, P.lhx, P.lb_z, nfield, P.nfp, tw_z, sx, sy, sz, kvx, kvy, kvz,
+                     w.kpart);
   ENUF_TRY(hipGetLastError());
   mark(5);
-  // inverse y (4 components), inverse x c2r -> interleaved fields
-  {
-    const int nby = nb_axis(g.M[1], hx, cs);
-    hipLaunchKernelGGL((k_fft_axis<R, 1>), dim3(hx / nby, g.M[2], nfield), dim3(kBlock), 2 * g.M[1] * nby * cs,
-                       st, (Cx<R> *)w.fspec, g.M[1], hx, (size_t)hx * g.M[1], halfG, tw_y, nby);
-    const int nb = nb_xc2r(g, cs);
-    const size_t sh = 2 * (size_t)hx * nb * cs + (size_t)nb * g.M[0] * 4 * sizeof(R);
-    hipLaunchKernelGGL((k_fft_x_c2r4<R>), dim3(g.M[1] * g.M[2] / nb), dim3(kBlock), sh, st,
-                       (const Cx<R> *)w.fspec, (real4<R> *)w.field, g, tw_xh, tw_x2, nb, nfield);
-  }
+  // inverse y (nfield components), inverse x c2r -> interleaved fields
+  hipLaunchKernelGGL((k_fft_y<R, 1>), dim3(hx >> P.lb_y, g.M[2], nfield), dim3(kBlock), P.lds_y, st,
+                     (Cx<R> *)w.fspec, P.lny, P.lhx, (size_t)hx * g.M[1], halfG, tw_y, P.lb_y);
+  hipLaunchKernelGGL((k_fft_x_c2r4<R>), dim3((g.M[1] * g.M[2]) >> P.lb_c2r), dim3(kBlock), P.lds_c2r, st,
+                     (const Cx<R> *)w.fspec, (real4<R> *)w.field, g, P.lnh, P.lb_c2r, nfield, tw_xh, tw_x2);
   ENUF_TRY(hipGetLastError());
   mark(6);
   // gather
@@ -1534,9 +1672,8 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
                        w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
   ENUF_TRY(hipGetLastError());
   mark(8);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, (const double *)w.kpart,
-                     nblk_z(g, sizeof(R) == 8), (const double *)w.rpart, nblk_pair(g), (const double *)w.scal, g,
-                     E);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, (const double *)w.kpart, P.zblocks,
+                     (const double *)w.rpart, nblk_pair(g), (const double *)w.scal, g, E);
   ENUF_TRY(hipGetLastError());
   mark(9);
   return hipSuccess;
