@@ -161,7 +161,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   ok = ok && need(dalloc(c, &w.off_c, (size_t)2 * g.ncells + 1));
   ok = ok && need(dalloc(c, &w.counts, 4));
   ok = ok && need(dalloc(c, &w.scal, 4));
-  ok = ok && need(dalloc(c, &w.qpart, (size_t)2 * enuf::nblk_prep(g)));
+  ok = ok && need(dalloc(c, &w.qpart, (size_t)3 * enuf::nblk_prep(g)));
   ok = ok && need(dalloc(c, &w.kpart, (size_t)enuf::nblk_z(g, precision == ENUF_FP64)));
   ok = ok && need(dalloc(c, &w.rpart, (size_t)enuf::nblk_pair(g)));
   ok = ok && need(dalloc(c, (unsigned char **)&w.grid, G * rs));

@@ -56,8 +56,8 @@ struct Work {
   int *runs = nullptr;      // [5*nruns] spread neighbour runs (dx, dy, dz, class lo, class hi)
   int nruns = 0;
   int *counts = nullptr;    // [4]: active, charged, flags, spare
-  double *scal = nullptr;   // [4]: Q, Q2, spare
-  double *qpart = nullptr;  // [2*nblk_prep] partial sums of q, q^2
+  double *scal = nullptr;   // [4]: Q, Q2, max abs(q), spare
+  double *qpart = nullptr;  // [3*nblk_prep] partial sums of q, q^2 and max abs(q)
   double *kpart = nullptr;  // [nblk_z] partial reciprocal energies
   double *rpart = nullptr;  // [ncells] partial real-space energies
   void *grid = nullptr;     // real [G]

@@ -67,6 +67,22 @@ __device__ double block_sum(double v) {
   return s;
 }
 
+__device__ double block_max(double v) {
+  __shared__ double red[16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) s = fmax(s, red[i]);
+  }
+  __syncthreads();
+  return s;
+}
+
 // Periodic wrap of one coordinate into [0, L).  Positions already inside the
 // box pass through unchanged (bit for bit), so pair distances between them
 // carry no wrap rounding.
@@ -192,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const 
                                                  int *__restrict__ rank_c, int *cnt_t, int *cnt_c,
                                                  R *F, R *phi, double *qpart, int *counts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double qs = 0.0, q2 = 0.0;
+  double qs = 0.0, q2 = 0.0, qa = 0.0;
   if (i < g.n) {
     const R px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2], qi = q[i];
     const bool fin = isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(qi);
@@ -201,6 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const 
     if (fin) {
       qs = (double)qi;
       q2 = (double)qi * (double)qi;
+      qa = fabs((double)qi);
     }
     if (active) {
       const R p3[3] = {px, py, pz};
@@ -232,9 +249,11 @@ __global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const 
   }
   const double a = block_sum(qs);
   const double b = block_sum(q2);
+  const double m = block_max(qa);
   if (threadIdx.x == 0) {
-    qpart[2 * blockIdx.x] = a;
-    qpart[2 * blockIdx.x + 1] = b;
+    qpart[3 * blockIdx.x] = a;
+    qpart[3 * blockIdx.x + 1] = b;
+    qpart[3 * blockIdx.x + 2] = m;
   }
 }
 
@@ -323,18 +342,21 @@ __global__ __launch_bounds__(1024) void k_scan2(int *bsum, const int *bev, int b
   }
   int ev = 0;
   for (int i = threadIdx.x; i < bt; i += blockDim.x) ev += bev[i];
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, m = 0.0;
   for (int i = threadIdx.x; i < nqp; i += blockDim.x) {
-    a += qpart[2 * i];
-    b += qpart[2 * i + 1];
+    a += qpart[3 * i];
+    b += qpart[3 * i + 1];
+    m = fmax(m, qpart[3 * i + 2]);
   }
   const double evd = block_sum((double)ev);
   a = block_sum(a);
   b = block_sum(b);
+  m = block_max(m);
   if (threadIdx.x == 0) {
     counts[1] = (int)evd;
     scal[0] = a;
     scal[1] = b;
+    scal[2] = m;
   }
 }
 
@@ -563,6 +585,191 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
 #pragma unroll
     for (int k = 0; k < NB / 64; ++k) v += acc[k][e];
     grid[((size_t)(t0[2] + iz) * g.M[1] + (t0[1] + iy)) * g.M[0] + t0[0] + ix] = v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// spread on the matrix cores (FP32 path), same tiles and particle runs as
+// k_spread.  With the window weights of particle k embedded in tile
+// coordinates (e^x_k: 16 values, e^y_k, e^z_k: 8 values, zero outside the
+// stencil and outside the tile),
+//   rho[x][y, z] = sum_k e^x_k[x] * e^y_k[y] * (q_k e^z_k[z])
+// is the product of a 16 x K and a K x 64 matrix over the K particles that
+// reach the tile.  Each wavefront accumulates all 16 x 64 outputs in MFMA
+// registers (16x16x16 f16 blocks, four column blocks) over its share of the
+// 16-particle steps; the four partial tiles are summed through LDS at the end.
+// Operands are split into f16 high and low parts, a = a_h + a_l, and each
+// product is taken as a_h b_h + a_h b_l + a_l b_h (about 21 significant bits;
+// the accumulation is FP32).  Charges are scaled by 2^-e, 2^e > max|q|, so
+// that every operand is at most 1 in magnitude; the tile is scaled back on
+// output.
+// --------------------------------------------------------------------------
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kSpreadK = 256;             // particles staged per round (one per thread)
+constexpr int kSpreadLd = kSpreadK + 4;   // LDS row pitch of the staged columns (floats)
+
+__device__ __forceinline__ void split_f16(float4_t v, half4_t &hi, half4_t &lo) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const _Float16 h = (_Float16)v[r];
+    hi[r] = h;
+    lo[r] = (_Float16)(v[r] - (float)h);  // v - h is exact in FP32
+  }
+}
+
+// Particle ranges of the runs that reach tile (tx, ty, tz) and the exclusive
+// prefix of their lengths: rpre[nruns] is the candidate count.
+__device__ void tile_runs(const int *__restrict__ off_t, const int *__restrict__ runs, int nruns, const Geom &g,
+                          int tx, int ty, int tz, int *rstart, int *rpre) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < nruns; k += blockDim.x) {
+    const int *rr = runs + 5 * k;
+    const int nx = wrapi(tx + rr[0], g.nt[0]);
+    const int ny = wrapi(ty + rr[1], g.nt[1]);
+    const int nz = wrapi(tz + rr[2], g.nt[2]);
+    const int tt = (nz * g.nt[1] + ny) * g.nt[0] + nx;
+    const int s0 = off_t[tt * kTileBins + rr[3]];
+    const int s1 = off_t[tt * kTileBins + rr[4] + 1];
+    rstart[k] = s0;
+    rpre[k + 1] = s1 - s0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    int carry = 0;
+    for (int c0 = 0; c0 < nruns; c0 += 64) {
+      const int k = c0 + tid;
+      const int v = k < nruns ? rpre[k + 1] : 0;
+      int inc = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (tid >= o) inc += u;
+      }
+      if (k < nruns) rpre[k + 1] = carry + inc;
+      carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) rpre[0] = 0;
+  }
+  __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ part, const int *__restrict__ off_t,
+                                                     const int *__restrict__ runs, int nruns, Geom g,
+                                                     const double *__restrict__ scal, float *__restrict__ grid) {
+  // rows 0..15: e^x, 16..23: e^y, 24..31: q e^z, one column per staged particle
+  __shared__ __align__(16) float E[32][kSpreadLd];
+  __shared__ int rstart[kMaxRuns], rpre[kMaxRuns + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int t = blockIdx.x;
+  const int tx = t % g.nt[0];
+  t /= g.nt[0];
+  const int ty = t % g.nt[1];
+  const int tz = t / g.nt[1];
+  const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
+  for (int e = tid; e < 32 * kSpreadLd; e += blockDim.x) (&E[0][0])[e] = 0.0f;
+  tile_runs(off_t, runs, nruns, g, tx, ty, tz, rstart, rpre);
+  const int total = rpre[nruns];
+  int qe;
+  (void)frexp(scal[2], &qe);  // 2^qe > max|q| (qe = 0 when there are no charges)
+  const float qscale = ldexpf(1.0f, -qe);
+  const int row0[3] = {0, 16, 24};
+
+  float4_t acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int base = 0; base < total; base += kSpreadK) {
+    const int c = base + tid;
+    int start[3] = {0, 0, 0};
+    float fr[3] = {0.0f, 0.0f, 0.0f}, qv = 0.0f;
+    bool hit = false;
+    if (c < total) {
+      int lo = 0, hi = nruns;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rpre[mid] <= c) lo = mid; else hi = mid;
+      }
+      const float4 v = part[rstart[lo] + (c - rpre[lo])];
+      const float s[3] = {v.x, v.y, v.z};
+      hit = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float fl = floorf(s[d]);
+        fr[d] = s[d] - fl;
+        // stencil start relative to the tile, wrapped into [T - M, T)
+        int rel = (int)fl - P / 2 + 1 - t0[d];
+        if (rel < 0) rel += g.M[d];
+        if (rel < 0) rel += g.M[d];
+        if (rel >= g.M[d]) rel -= g.M[d];
+        start[d] = rel < g.T[d] ? rel : rel - g.M[d];
+        hit = hit && start[d] + P > 0;
+      }
+      qv = v.w * qscale;
+    }
+    // deterministic compaction of the hits into columns 0 .. ns-1
+    int ns;
+    const int slot = block_exscan_int(hit ? 1 : 0, &ns);
+    if (hit) {
+#pragma unroll
+      for (int r = 0; r < 32; ++r) E[r][slot] = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float w[P];
+        bspline<float, P>(fr[d], w);
+        const float sc = d == 2 ? qv : 1.0f;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int idx = start[d] + j;
+          if (idx >= 0 && idx < g.T[d]) E[row0[d] + idx][slot] = w[j] * sc;
+        }
+      }
+    }
+    __syncthreads();
+    const int nsteps = (ns + 15) >> 4;
+    for (int ks = wv; ks < nsteps; ks += 4) {
+      const int k0 = 16 * ks + 4 * (lane >> 4);
+      float4_t a = *reinterpret_cast<const float4_t *>(&E[lane & 15][k0]);
+      // columns past the staged count may hold stale (finite) weights
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (k0 + r >= ns) a[r] = 0.0f;
+      const float4_t by = *reinterpret_cast<const float4_t *>(&E[16 + (lane & 7)][k0]);
+      half4_t ah, al;
+      split_f16(a, ah, al);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const float4_t bz = *reinterpret_cast<const float4_t *>(&E[24 + 2 * nb + ((lane >> 3) & 1)][k0]);
+        half4_t bh, bl;
+        split_f16(by * bz, bh, bl);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, acc[nb], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // partial tiles of the four waves -> LDS [wave][z][y][x], summed and written
+  float *red = &E[0][0];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int y = lane & 7, z = 2 * nb + ((lane >> 3) & 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x = 4 * (lane >> 4) + r;
+      red[wv * 1024 + (z * 8 + y) * 16 + x] = acc[nb][r];
+    }
+  }
+  __syncthreads();
+  const float out_scale = ldexpf(1.0f, qe);
+  for (int e = tid; e < 1024; e += blockDim.x) {
+    const int x = e & 15, y = (e >> 4) & 7, z = e >> 7;
+    if (x < g.T[0] && y < g.T[1] && z < g.T[2]) {
+      const float v = (red[e] + red[1024 + e]) + (red[2048 + e] + red[3072 + e]);
+      grid[((size_t)(t0[2] + z) * g.M[1] + (t0[1] + y)) * g.M[0] + t0[0] + x] = v * out_scale;
+    }
   }
 }
 
@@ -1540,8 +1747,12 @@ template void fill_tables<double>(const Geom &, const size_t[kTabSlots], double 
 
 template <typename R, int P>
 static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(spread_block<R>()), 0, st,
-                     (const real4<R> *)w.part_t, w.off_t, (const int *)w.runs, w.nruns, g, (R *)w.grid);
+  if constexpr (sizeof(R) == 4)
+    hipLaunchKernelGGL((k_spread_mfma<P>), dim3(g.ntiles), dim3(256), 0, st, (const float4 *)w.part_t, w.off_t,
+                       (const int *)w.runs, w.nruns, g, (const double *)w.scal, (float *)w.grid);
+  else
+    hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(spread_block<R>()), 0, st,
+                       (const real4<R> *)w.part_t, w.off_t, (const int *)w.runs, w.nruns, g, (R *)w.grid);
 }
 template <typename R, int P>
 static size_t gather_tile_lds(const Geom &g) {
