@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """ENUF energy+force throughput on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload charged_fluid]
+    python bench.py [--steps K] [--warmup W] [--workload ions_1m]
 
 One step = one full ENUF evaluation (enuf_energy_forces: wrap and sort,
 spread, forward FFT, influence + energy, inverse FFTs, gather, real-space pair
@@ -30,10 +30,13 @@ FP32_VALU_TFLOPS = 157.3       # MI355X vector FP32
 FP64_VALU_TFLOPS = 78.6
 PAIR_FLOPS = 40.0              # flops per evaluated pair (erfc, exp, rsqrt, accumulation)
 
-# Bench workloads: the 1M-bead charged fluid is the headline; the others are
-# its smaller and larger siblings.
+# Bench workloads: one million ions (every bead of the 1M-bead fluid charged,
+# at the searched FP32 setting) is the headline; charged_fluid is the same
+# geometry with 20% of the beads charged; the others are smaller and larger
+# systems.
 WORKLOADS = {
     "charged_fluid": dict(gen="charged_fluid", kw=dict(alpha=0.95)),
+    "ions_1m": dict(gen="ions_1m", kw={}),
     "electrolyte": dict(gen="electrolyte", kw={}),
     "nacl": dict(gen="nacl", kw={}),
     "anisotropic": dict(gen="anisotropic", kw={}),
@@ -105,24 +108,75 @@ def cpu_baseline(w, budget_s=20.0):
 
 def golden_check(w, F, E):
     """RMS relative force error and relative energy error against stored oracle
-    values for this workload (tests/golden/<workload>_oracle.npz), if present."""
+    values for this workload (tests/golden/<workload>_oracle.npz), if present.
+    Files holding only F_conv (the converged Ewald force, whatever splitting
+    parameter the oracle used) are compared on forces alone."""
     path = os.path.join(ROOT, "tests", "golden", f"{w.name}_oracle.npz")
     if not os.path.exists(path):
         return None
     g = np.load(path)
-    if not (np.isclose(float(g["alpha"]), w.alpha) and np.isclose(float(g["r_c"]), w.r_c)
-            and int(g["N"]) == w.N and int(g["seed"]) == w.seed):
+    if int(g["N"]) != w.N or int(g["seed"]) != w.seed:
         return None
     s = g["sample"]
     Fs = F[s]
-    eps_f = float(np.linalg.norm(Fs - g["F"]) / np.linalg.norm(g["F"]))
-    out = {"rms_force_err": eps_f, "force_sample": int(len(s)), "ref_tol": float(g["tol"])}
+    out = {"force_sample": int(len(s)), "ref_tol": float(g["tol"])}
+    if "F" in g.files:
+        if not (np.isclose(float(g["alpha"]), w.alpha) and np.isclose(float(g["r_c"]), w.r_c)):
+            return None
+        out["rms_force_err"] = float(np.linalg.norm(Fs - g["F"]) / np.linalg.norm(g["F"]))
     if "F_conv" in g.files:
-        # against the same Ewald sum with the real-space cut converged
+        # against the Ewald sum with the real-space cut converged
         out["rms_force_err_rc_converged"] = float(np.linalg.norm(Fs - g["F_conv"]) / np.linalg.norm(g["F_conv"]))
+        out.setdefault("rms_force_err", out["rms_force_err_rc_converged"])
     if "E" in g.files:
         out["energy_rel_err"] = float(abs(E - float(g["E"])) / abs(float(g["E"])))
     return out
+
+
+SEARCH_GRID = dict(M=(128, 256), p=(4, 6), r_c=(1.5, 1.8, 2.1, 2.4, 2.7, 3.0), alpha_rc=(2.6, 2.9, 3.2))
+
+
+def search(args, target=1e-4, steps=5):
+    """Grid search over ENUF settings for one workload (FP32): each setting is
+    timed over `steps` evaluations (HIP events around the calls) and its RMS
+    force error taken against the stored oracle forces."""
+    import itertools
+
+    import torch
+
+    from paper_2004_12484_amd import enuf, inputs
+
+    spec = WORKLOADS[args.workload]
+    w0 = getattr(inputs, spec["gen"])(**spec["kw"])
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(w0.x, dtype=torch.float32, device=dev)
+    q = torch.tensor(w0.q, dtype=torch.float32, device=dev)
+    best = None
+    for M, p, rc, arc in itertools.product(*SEARCH_GRID.values()):
+        if rc > 0.5 * float(np.min(w0.box)):
+            continue
+        alpha = arc / rc
+        eng = enuf.Enuf(w0.box, w0.N, alpha, rc, (M, M, M), p, precision="f32", device=dev)
+        for _ in range(2):
+            E, F, _ = eng.energy_forces(x, q)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            E, F, _ = eng.energy_forces(x, q)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        eng.close()
+        w0.alpha, w0.r_c, w0.M, w0.p = alpha, rc, (M, M, M), p
+        acc = golden_check(w0, F.double().cpu().numpy(), float(E[0].item()))
+        err = acc["rms_force_err"] if acc else None
+        rec = {"M": M, "p": p, "r_c": rc, "alpha": alpha, "ms": ms, "rms_force_err": err}
+        print(json.dumps(rec), flush=True)
+        if err is not None and err <= target and (best is None or ms < best["ms"]):
+            best = rec
+    print(json.dumps({"search_best": best, "target": target, "workload": args.workload}), flush=True)
 
 
 def main():
@@ -130,10 +184,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="charged_fluid", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ions_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--alpha", type=float, default=None)
+    ap.add_argument("--r-c", type=float, default=None)
+    ap.add_argument("--M", type=int, default=None)
+    ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--search", action="store_true",
+                    help="grid-search (alpha, r_c, M, p) for the workload: time each FP32 setting and its "
+                         "RMS force error against the stored oracle forces; print one JSON line per setting")
     ap.add_argument("--copy-probe", type=float, default=None, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times): the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -158,10 +218,15 @@ def main():
 
     from paper_2004_12484_amd import enuf, inputs
 
+    if args.search:
+        search(args)
+        return
+
     spec = WORKLOADS[args.workload]
     kw = dict(spec["kw"])
-    if args.alpha is not None:
-        kw["alpha"] = args.alpha
+    for key, val in (("alpha", args.alpha), ("r_c", args.r_c), ("M", args.M), ("p", args.p)):
+        if val is not None:
+            kw[key] = val
     if args.precision is not None:
         kw["precision"] = args.precision
     w = getattr(inputs, spec["gen"])(**kw)

@@ -80,8 +80,10 @@ def real_images(x, q, box, alpha, rc, ke=1.0):
     return float(e[0]), f, phi
 
 
-def real_minimage(x, q, box, alpha, rc, ke=1.0, sample=None):
-    """Real-space sum, minimum image (requires rc <= min(L)/2)."""
+def real_minimage(x, q, box, alpha, rc, ke=1.0, sample=None, energy=True):
+    """Real-space sum, minimum image (requires rc <= min(L)/2).  With
+    energy=False the O(N^2) pair energy is skipped (returned as nan) and only
+    the sampled forces and potentials are computed."""
     x, q, box = _prep(x, q, box)
     if rc > 0.5 * box.min() * (1 + 1e-12):
         raise ValueError("minimum image needs rc <= min(L)/2")
@@ -96,10 +98,10 @@ def real_minimage(x, q, box, alpha, rc, ke=1.0, sample=None):
     f = np.zeros((m, 3))
     phi = np.zeros(m)
     rc_ = _load().oracle_real_minimage(n, _p(x), _p(q), _p(box), alpha, rc, ke, ns, _p(sp),
-                                       _p(e), _p(f), _p(phi))
+                                       _p(e) if energy else None, _p(f), _p(phi))
     if rc_ != 0:
         raise MemoryError("oracle_real_minimage: allocation failed")
-    return float(e[0]), f, phi
+    return (float(e[0]) if energy else float("nan")), f, phi
 
 
 def kset_converged(box, alpha, tol=1e-16):

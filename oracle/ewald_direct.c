@@ -115,9 +115,9 @@ int oracle_real_minimage(int64_t n, const double *x, const double *q,
     if (!cid) return -1;
     nq = 0;
     for (int64_t i = 0; i < n; ++i) if (q[i] != 0.0) cid[nq++] = i;
-    /* energy: all charged pairs i < j */
+    /* energy: all charged pairs i < j (skipped when no energy is asked for) */
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : etot)
-    for (int64_t a = 0; a < nq; ++a) {
+    for (int64_t a = 0; a < (e_out ? nq : 0); ++a) {
         int64_t i = cid[a];
         double ei = 0.0;
         for (int64_t b = a + 1; b < nq; ++b) {

@@ -19,7 +19,7 @@ constexpr int kMaxTilePts = kTileX * kTileY * kTileZ;
 constexpr int kClasses = 27;         // stencil spill classes per tile (3 digits: low/none/high)
 constexpr int kTileBins = 2 * kClasses;  // sort bins per tile: charged classes, then neutral
 constexpr int kMaxRuns = 256;        // neighbour (tile, class-range) runs read by one spread tile
-constexpr int kPairBlock = 128;      // threads per cell in the pair kernel
+constexpr int kPairBlock = 256;      // threads per cell in the pair kernel
 constexpr int kPairChunk = 512;      // neighbour particles staged in LDS at a time
 constexpr int kScanBlock = 256;      // threads per scan block
 constexpr int kScanChunk = 4 * kScanBlock;  // bins per scan block

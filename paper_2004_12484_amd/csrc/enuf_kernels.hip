@@ -1358,6 +1358,17 @@ __device__ __forceinline__ double exp_fast(double v) { return exp(v); }
 __device__ __forceinline__ float rsqrt_r(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_r(double v) { return 1.0 / sqrt(v); }
 
+// 0 < r2 < rc2 in one unsigned compare of the bit patterns (non-negative
+// floats order like their bits; r2 = 0 wraps to the largest value)
+__device__ __forceinline__ bool in_cut(float r2, unsigned lim) { return __float_as_uint(r2) - 1u < lim; }
+__device__ __forceinline__ bool in_cut(double r2, unsigned long long lim) {
+  return (unsigned long long)__double_as_longlong(r2) - 1ull < lim;
+}
+__device__ __forceinline__ unsigned cut_limit(float rc2) { return __float_as_uint(rc2) - 1u; }
+__device__ __forceinline__ unsigned long long cut_limit(double rc2) {
+  return (unsigned long long)__double_as_longlong(rc2) - 1ull;
+}
+
 template <typename R, int MODE, bool MINIMG>
 __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict__ part,
                                                      const int *__restrict__ perm,
@@ -1430,14 +1441,17 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
   double e = 0.0;
 
   for (int hb = h0; hb < h1; hb += blockDim.x) {
+    // lane groups: every thread works on one home particle; home hi gets Gh
+    // groups (G or G+1), which split its candidates by index modulo Gh
     const int nh = min((int)blockDim.x, h1 - hb);
     const int G = blockDim.x / nh;
+    const int extra = blockDim.x - G * nh;
     const int hi = tid % nh, grp = tid / nh;
-    const bool act = grp < G;
+    const int Gh = G + (hi < extra ? 1 : 0);
     real4<R> me;
     int iout = 0;
     R prev[4] = {R(0), R(0), R(0), R(0)};
-    if (act) {
+    {
       me = part[hb + hi];
       if (grp == 0) {
         // the outputs this particle adds to, fetched now so their latency
@@ -1482,25 +1496,25 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
         cand[k] = u;
       }
       __syncthreads();
-      if (act) {
+      {
         // pass 1 marks the candidates inside the cutoff in a 32-bit mask;
         // pass 2 does the erfc/exp work for the marked ones only, so lanes
         // that miss do not idle through it
-        const int nmine = (nc - grp + G - 1) / G;  // candidates grp, grp+G, ...
+        const auto lim = cut_limit(rc2);
+        const int nmine = (nc - grp + Gh - 1) / Gh;  // candidates grp, grp+Gh, ...
         for (int m0 = 0; m0 < nmine; m0 += 32) {
           unsigned mask = 0u;
           const int mend = min(32, nmine - m0);
           for (int b = 0; b < mend; ++b) {
             R ddx, ddy, ddz;
-            sep(grp + G * (m0 + b), ddx, ddy, ddz);
-            const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            if (r2 < rc2 && r2 > R(0)) mask |= 1u << b;
+            sep(grp + Gh * (m0 + b), ddx, ddy, ddz);
+            if (in_cut(ddx * ddx + ddy * ddy + ddz * ddz, lim)) mask |= 1u << b;
           }
           while (mask) {
             const int b = __builtin_ctz(mask);
             mask &= mask - 1u;
             R ddx, ddy, ddz;
-            const R qj = sep(grp + G * (m0 + b), ddx, ddy, ddz);
+            const R qj = sep(grp + Gh * (m0 + b), ddx, ddy, ddz);
             const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             const R ir = rsqrt_r(r2);
             const R r = r2 * ir;
@@ -1522,8 +1536,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
     red[tid][2] = fz;
     red[tid][3] = ph;
     __syncthreads();
-    if (act && grp == 0) {
-      for (int k = 1; k < G; ++k) {
+    if (grp == 0) {
+      for (int k = 1; k < Gh; ++k) {
         fx += red[k * nh + hi][0];
         fy += red[k * nh + hi][1];
         fz += red[k * nh + hi][2];
@@ -1668,13 +1682,19 @@ static FftPlan fft_plan(const Geom &g, size_t cs, int nf) {
   auto zl = [&](int nfp, int lb) {
     return (size_t)(1 + (stz >= 2) * nfp + (stz == 3) * nfp) * nz * ((size_t)1 << lb) * cs;
   };
+  // z: the widest pencil batch (rows of up to 16 contiguous elements) that
+  // fits, batching the field pencils when there is room for them
   const int zp = (int)nh * g.M[1];
-  P.nfp = nf;
-  P.lb_z = pick(zp, [&](int lb) { return zl(nf, lb); }, 49152);
-  if (zl(nf, P.lb_z) > 49152 || (P.lb_z < 2 && zp >= 4)) {
-    P.nfp = 1;
-    P.lb_z = pick(zp, [&](int lb) { return zl(1, lb); }, 65536);
-  }
+  const size_t zbudget = 65536 - 512;  // leave room for the static reduction scratch
+  // (the field pencils batched when rows of 8 or more still fit, since the
+  // batch saves passes over the spectrum; else one field at a time)
+  P.nfp = 1;
+  P.lb_z = 0;
+  bool found = false;
+  for (int lb = 4; lb >= 3 && !found; --lb)
+    if (zp % (1 << lb) == 0 && zl(nf, lb) <= zbudget) { P.nfp = nf; P.lb_z = lb; found = true; }
+  for (int lb = 4; lb >= 0 && !found; --lb)
+    if (zp % (1 << lb) == 0 && zl(1, lb) <= zbudget) { P.nfp = 1; P.lb_z = lb; found = true; }
   P.lds_z = zl(P.nfp, P.lb_z);
   P.zblocks = zp >> P.lb_z;
   auto c2r = [&](int lb) { return 2 * (size_t)nf * nh * pad_ld(lb) * cs; };

@@ -17,6 +17,7 @@ the ENUF hot path is measured on:
               alpha trials, Sec. 2.4.2)
   electrolyte bulk 1:1 point-charge electrolyte, uniform random positions
   charged_fluid  mesoscopic bead fluid, a fraction of the beads charged +-1
+  ions_1m     the same geometry with every bead charged: one million ions
   anisotropic orthorhombic box with +1 bead chains (random walks), -1
               counterions and neutral solvent
   random_system  random neutral systems for the parameter-selection sweeps
@@ -36,6 +37,7 @@ __all__ = [
     "nacl",
     "electrolyte",
     "charged_fluid",
+    "ions_1m",
     "anisotropic",
     "random_system",
     "workload",
@@ -135,6 +137,22 @@ def charged_fluid(N: int = 1 << 20, L: float = 70.0, charged_fraction: float = 0
                     (M, M, M), p, precision, seed)
 
 
+def ions_1m(N: int = 1 << 20, L: float = 70.0, seed: int = 3, r_c: float = 2.1, alpha: float = 2.9 / 2.1,
+            M: int = 256, p: int = 4, precision: str = "f32") -> Workload:
+    """One million ions: the charged-fluid geometry (uniform positions, same
+    seed) with every bead charged, half +1 and half -1 by a seeded
+    permutation.  The default (alpha, r_c, M, p) is the fastest FP32 setting
+    of a grid search whose RMS force error against the oracle is <= 1e-4."""
+    box = np.array([L, L, L], float)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, size=(N, 3)) * box[None, :]
+    q = np.empty(N)
+    sel = rng.permutation(N)
+    q[sel[: N // 2]] = 1.0
+    q[sel[N // 2:]] = -1.0
+    return Workload("ions_1m", _wrap(x, box), q, box, alpha, r_c, (M, M, M), p, precision, seed)
+
+
 def anisotropic(N: int = 1 << 22, box=(120.0, 120.0, 240.0), chain_fraction: float = 0.02,
                 chain_len: int = 32, bond: float = 1.0, seed: int = 5,
                 r_c: float = 3.0, alpha: float = 1.0, M=(256, 256, 512), p: int = 6,
@@ -194,6 +212,7 @@ WORKLOADS = {
     "nacl": nacl,
     "electrolyte": electrolyte,
     "charged_fluid": charged_fluid,
+    "ions_1m": ions_1m,
     "anisotropic": anisotropic,
 }
 

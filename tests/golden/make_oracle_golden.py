@@ -26,6 +26,29 @@ SPECS = {
     "electrolyte": (dict(), 2048, 1e-16),
     "charged_fluid": (dict(alpha=0.95), 512, 1e-10),
 }
+# forces only, at a splitting parameter of the oracle's own choosing: the
+# converged Ewald force does not depend on alpha, so a small alpha keeps the
+# k-space sum over all N charges affordable (the real-space part is cut where
+# erfc(alpha r) < 1e-10)
+FORCE_ONLY = {
+    "ions_1m": (dict(), 512, 0.4, 1e-10),
+}
+
+
+def make_forces(name):
+    kw, ns, alpha, tol = FORCE_ONLY[name]
+    w = getattr(inputs, name)(**kw)
+    charged = np.nonzero(w.q)[0]
+    sample = np.sort(np.random.default_rng(123).choice(charged, ns, replace=False))
+    rc = min(0.5 * float(np.min(w.box)), 4.6 / alpha)
+    t = time.time()
+    _, f_r, _ = ewald.real_minimage(w.x, w.q, w.box, alpha, rc, w.ke, sample=sample, energy=False)
+    _, f_k, _ = ewald.recip(w.x, w.q, w.box, alpha, w.ke, tol=tol, sample=sample)
+    dt = time.time() - t
+    path = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(path, sample=sample.astype(np.int64), F_conv=f_r + f_k, alpha_oracle=alpha,
+                        rc_conv=rc, N=w.N, seed=w.seed, tol=tol)
+    print(f"{name}: forces on {len(sample)} sampled ions, oracle {dt:.1f} s -> {path}", flush=True)
 
 
 def make(name):
@@ -52,5 +75,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(SPECS)):
-        make(n)
+    for n in (sys.argv[1:] or list(SPECS) + list(FORCE_ONLY)):
+        make_forces(n) if n in FORCE_ONLY else make(n)

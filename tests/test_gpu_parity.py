@@ -181,6 +181,38 @@ def test_permutation_invariance():
     assert np.abs(a["F"][perm] - b["F"]).max() <= 1e-10 * np.abs(a["F"]).max()
 
 
+# ---------------------------------------------------------------- pair search
+# The real-space sum runs over cells of side >= r_c; with fewer than 3 cells
+# on an axis the minimum image is taken per pair on that axis.  These cases
+# pin 2 cells on an axis (minimum image), exactly 3 (every neighbour cell is
+# a distinct image), the general case, neutral home particles (potentials
+# requested), and a density at which a cell's neighbours fill many LDS
+# staging chunks.
+@pytest.mark.parametrize("box,rc,n", [
+    ((10.0, 11.0, 13.0), 4.0, 1500),   # 2, 2, 3 cells
+    ((12.0, 15.0, 18.5), 2.9, 1800),   # 4, 5, 6 cells
+    ((9.0, 14.0, 11.0), 3.0, 1400),    # 3, 4, 3 cells
+])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_search_geometries_vs_mirror(box, rc, n, prec):
+    x, q, box = _random_system(n, box, seed=int(rc * 10), neutral_frac=0.3)
+    eng, out = run(x, q, box, 3.0 / rc, rc, (32, 32, 32), 4, precision=prec)
+    xr, qr = _as_precision(x, q, prec)
+    m = em.enuf(xr, qr, box, 3.0 / rc, rc, (32, 32, 32), 4, want_grad=False)
+    _compare(out, m, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dense_pair_search_many_chunks_vs_mirror(prec):
+    # 12 charges per unit volume, r_c = 3: ~8700 neighbour candidates per
+    # cell, staged through LDS in many chunks
+    x, q, box = _random_system(12 * 15 * 15 * 15, (15.0, 15.0, 15.0), seed=11)
+    eng, out = run(x, q, box, 1.0, 3.0, (32, 32, 32), 4, precision=prec)
+    xr, qr = _as_precision(x, q, prec)
+    m = em.enuf(xr, qr, box, 1.0, 3.0, (32, 32, 32), 4, want_grad=False)
+    _compare(out, m, prec)
+
+
 # ---------------------------------------------------------------- edges
 def test_single_charge_wigner():
     L = 5.0
