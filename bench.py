@@ -36,7 +36,7 @@ PAIR_FLOPS = 40.0              # flops per evaluated pair (erfc, exp, rsqrt, acc
 # systems.
 WORKLOADS = {
     "charged_fluid": dict(gen="charged_fluid", kw=dict(alpha=0.95)),
-    "ions_1m": dict(gen="ions_1m", kw={}),
+    "ions_1m": dict(gen="ions_1m", kw={}, force_mode="analytic"),
     "electrolyte": dict(gen="electrolyte", kw={}),
     "nacl": dict(gen="nacl", kw={}),
     "anisotropic": dict(gen="anisotropic", kw={}),
@@ -133,7 +133,8 @@ def golden_check(w, F, E):
     return out
 
 
-SEARCH_GRID = dict(M=(128, 256), p=(4, 6), r_c=(1.5, 1.8, 2.1, 2.4, 2.7, 3.0), alpha_rc=(2.6, 2.9, 3.2))
+SEARCH_GRID = dict(mode=("ik", "analytic"), M=(128, 256), p=(4, 6), r_c=(1.5, 1.8, 2.1, 2.4, 2.7, 3.0),
+                   alpha_rc=(2.6, 2.9, 3.2))
 
 
 def search(args, target=1e-4, steps=5):
@@ -152,11 +153,11 @@ def search(args, target=1e-4, steps=5):
     x = torch.tensor(w0.x, dtype=torch.float32, device=dev)
     q = torch.tensor(w0.q, dtype=torch.float32, device=dev)
     best = None
-    for M, p, rc, arc in itertools.product(*SEARCH_GRID.values()):
+    for mode, M, p, rc, arc in itertools.product(*SEARCH_GRID.values()):
         if rc > 0.5 * float(np.min(w0.box)):
             continue
         alpha = arc / rc
-        eng = enuf.Enuf(w0.box, w0.N, alpha, rc, (M, M, M), p, precision="f32", device=dev)
+        eng = enuf.Enuf(w0.box, w0.N, alpha, rc, (M, M, M), p, precision="f32", device=dev, force_mode=mode)
         for _ in range(2):
             E, F, _ = eng.energy_forces(x, q)
         torch.cuda.synchronize()
@@ -172,7 +173,7 @@ def search(args, target=1e-4, steps=5):
         w0.alpha, w0.r_c, w0.M, w0.p = alpha, rc, (M, M, M), p
         acc = golden_check(w0, F.double().cpu().numpy(), float(E[0].item()))
         err = acc["rms_force_err"] if acc else None
-        rec = {"M": M, "p": p, "r_c": rc, "alpha": alpha, "ms": ms, "rms_force_err": err}
+        rec = {"force_mode": mode, "M": M, "p": p, "r_c": rc, "alpha": alpha, "ms": ms, "rms_force_err": err}
         print(json.dumps(rec), flush=True)
         if err is not None and err <= target and (best is None or ms < best["ms"]):
             best = rec
@@ -190,6 +191,9 @@ def main():
     ap.add_argument("--r-c", type=float, default=None)
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--p", type=int, default=None)
+    ap.add_argument("--force-mode", default=None, choices=["ik", "analytic"],
+                    help="reciprocal forces: ik fields (three inverse transforms) or the analytic window "
+                         "derivative (one); default: the workload's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--search", action="store_true",
                     help="grid-search (alpha, r_c, M, p) for the workload: time each FP32 setting and its "
@@ -236,7 +240,9 @@ def main():
     torch.cuda.set_device(dev)
     x = torch.tensor(w.x, dtype=dt, device=dev)
     q = torch.tensor(w.q, dtype=dt, device=dev)
-    eng = enuf.Enuf(w.box, w.N, w.alpha, w.r_c, w.M, w.p, precision=w.precision, device=dev)
+    force_mode = args.force_mode or spec.get("force_mode", "ik")
+    eng = enuf.Enuf(w.box, w.N, w.alpha, w.r_c, w.M, w.p, precision=w.precision, device=dev,
+                    force_mode=force_mode)
     E = torch.empty(5, dtype=torch.float64, device=dev)
     F = torch.empty((w.N, 3), dtype=dt, device=dev)
     lib = enuf.load_library()
@@ -298,6 +304,7 @@ def main():
         "vs_baseline": None, "dtype": "f32" if rs == 4 else "f64", "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "n_charged": nq, "box": [float(b) for b in w.box],
                    "M": list(w.M), "p": w.p, "alpha": w.alpha, "r_c": w.r_c, "precision": w.precision,
+                   "force_mode": force_mode,
                    "seed": w.seed, "parallelism": "single GPU"},
         "ns_per_particle": ms * 1e6 / w.N, "ns_per_charged": ms * 1e6 / max(nq, 1),
         "wall_s": wall, "phase_ms": phases, "phase_gbs": hbm,

@@ -68,8 +68,20 @@ typedef enum {
                                     evaluation in a ring of n slots; 0: off
                                     (default) */
     ENUF_OPT_GRAPH = 2,       /* 1: replay the launch sequence as a HIP graph; default 0 */
-    ENUF_OPT_CHECK = 3        /* 1: enuf_energy_forces synchronises and reports
+    ENUF_OPT_CHECK = 3,       /* 1: enuf_energy_forces synchronises and reports
                                     ENUF_ENONFINITE itself; default 0 */
+    ENUF_OPT_FORCE_MODE = 4   /* reciprocal forces.  0 (default): ik
+                                 differentiation as in the paper's Eq. 41-42:
+                                 three field grids are transformed back and
+                                 interpolated; the forces sum to zero up to
+                                 rounding.  1: analytic differentiation of the
+                                 window: only the potential grid psi is
+                                 transformed back and the gather uses the
+                                 window's derivative, so the forces are the
+                                 exact negative gradient of the computed
+                                 energy; their sum is zero only to the
+                                 method's accuracy.  One inverse transform
+                                 instead of three. */
 } enuf_option;
 
 /* Internal buffers enuf_stage_copy() can read (for tests of single steps). */
@@ -80,7 +92,9 @@ typedef enum {
                                  (it happens fused with the influence step) */
     ENUF_STAGE_FIELDS = 2,    /* real-space fields after the inverse FFTs, real
                                  [Mz][My][Mx][4] = (E_x, E_y, E_z, psi); psi is
-                                 0 unless the evaluation requested phi */
+                                 0 unless the evaluation requested phi.  After
+                                 an evaluation in force mode 1: psi alone,
+                                 real [Mz][My][Mx] */
     ENUF_STAGE_SORTED = 3,    /* int32 [N] permutation, grid-tile order
                                  (entries past the active count are unused) */
     ENUF_STAGE_COUNTS = 4,    /* int32 [2]: active particles, charged particles */

@@ -25,6 +25,8 @@ struct enuf_ctx_s {
   bool have_forward = false;
   bool last_all_active = false;
   bool check = false;
+  bool analytic = false;       // ENUF_OPT_FORCE_MODE = 1
+  bool last_analytic = false;  // the last forward left psi as a plain real grid
   // timing ring: `slots` evaluations x (kPhases + 1) events
   std::vector<hipEvent_t> ring;
   int slots = 0, next = 0, recorded = 0;
@@ -246,6 +248,10 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "check is 0 or 1");
       ctx->check = value == 1.0;
       return ENUF_OK;
+    case ENUF_OPT_FORCE_MODE:
+      if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "force mode is 0 (ik) or 1 (analytic)");
+      ctx->analytic = value == 1.0;
+      return ENUF_OK;
   }
   return fail(ctx, ENUF_EINVAL, "unknown option");
 }
@@ -282,15 +288,17 @@ enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, doubl
     ctx->next = (ctx->next + 1) % ctx->slots;
     ctx->recorded = std::min(ctx->recorded + 1, ctx->slots);
   }
+  const bool an = ctx->analytic;
   if (ctx->prec == ENUF_FP64)
     e = enuf::launch_forward<double>(ctx->g, ctx->w, ctx->st, (const double *)x, (const double *)q, E,
-                                     (double *)F, (double *)phi, all, all, ev);
+                                     (double *)F, (double *)phi, all, all, an, ev);
   else
     e = enuf::launch_forward<float>(ctx->g, ctx->w, ctx->st, (const float *)x, (const float *)q, E,
-                                    (float *)F, (float *)phi, all, all, ev);
+                                    (float *)F, (float *)phi, all, all, an, ev);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->have_forward = true;
   ctx->last_all_active = all;
+  ctx->last_analytic = an;
   if (ctx->check) {
     int32_t f = 0;
     enuf_status s = read_flags(ctx, &f, true);
@@ -309,9 +317,11 @@ enuf_status enuf_energy_grad(enuf_ctx ctx, double grad_E, void *dEdx, void *dEdq
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (ctx->prec == ENUF_FP64)
-    e = enuf::launch_adjoint<double>(ctx->g, ctx->w, ctx->st, grad_E, (double *)dEdx, (double *)dEdq);
+    e = enuf::launch_adjoint<double>(ctx->g, ctx->w, ctx->st, grad_E, (double *)dEdx, (double *)dEdq,
+                                     ctx->last_analytic);
   else
-    e = enuf::launch_adjoint<float>(ctx->g, ctx->w, ctx->st, grad_E, (float *)dEdx, (float *)dEdq);
+    e = enuf::launch_adjoint<float>(ctx->g, ctx->w, ctx->st, grad_E, (float *)dEdx, (float *)dEdq,
+                                    ctx->last_analytic);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   return ENUF_OK;
 }
@@ -328,7 +338,7 @@ enuf_status enuf_stage_bytes(enuf_ctx ctx, int32_t stage, size_t *bytes) {
   switch (stage) {
     case ENUF_STAGE_GRID: *bytes = G * rs; return ENUF_OK;
     case ENUF_STAGE_SPECTRUM: *bytes = G / 2 * 2 * rs; return ENUF_OK;
-    case ENUF_STAGE_FIELDS: *bytes = G * 4 * rs; return ENUF_OK;
+    case ENUF_STAGE_FIELDS: *bytes = G * (ctx->last_analytic ? 1 : 4) * rs; return ENUF_OK;
     case ENUF_STAGE_SORTED: *bytes = (size_t)ctx->g.n * 4; return ENUF_OK;
     case ENUF_STAGE_COUNTS: *bytes = 2 * 4; return ENUF_OK;
     case ENUF_STAGE_CELLS: *bytes = (size_t)ctx->g.n * 4; return ENUF_OK;

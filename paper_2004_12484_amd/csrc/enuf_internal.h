@@ -83,15 +83,19 @@ size_t table_size(const Geom &g, size_t off[kTabSlots]);
 template <typename R> void fill_tables(const Geom &g, const size_t off[kTabSlots], R *host);
 
 // One forward evaluation: every phase enqueued on `st`.  `ev` (optional) is
-// an array of kPhases+1 events recorded between phases.
+// an array of kPhases+1 events recorded between phases.  analytic: forces
+// from the window derivative on the potential grid (one inverse transform,
+// psi left as a plain real grid) instead of the three ik field grids.
 constexpr int kPhases = 9;
 template <typename R>
 hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R *x, const R *q,
-                          double *E, R *F, R *phi, bool all_active, bool want_psi, hipEvent_t *ev);
+                          double *E, R *F, R *phi, bool all_active, bool want_psi, bool analytic,
+                          hipEvent_t *ev);
 
-// Adjoint of the last forward: dEdx, dEdq (either may be null).
+// Adjoint of the last forward: dEdx, dEdq (either may be null).  psi_scalar:
+// the last forward left psi as a plain real grid (analytic mode).
 template <typename R>
 hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double gscale, R *dEdx,
-                          R *dEdq);
+                          R *dEdq, bool psi_scalar);
 
 }  // namespace enuf

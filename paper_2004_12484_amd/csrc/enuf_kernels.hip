@@ -34,6 +34,11 @@ template <typename R> using real4 = typename V4<R>::T;
 
 template <typename R> struct Cx { R x, y; };
 
+// the potential component of a field grid point: .w of the interleaved
+// (E_x, E_y, E_z, psi) layout, or the value itself on a potential-only grid
+template <typename R> __device__ __forceinline__ R psi_of(const real4<R> &f) { return f.w; }
+template <typename R> __device__ __forceinline__ R psi_of(R f) { return f; }
+
 template <typename R> __device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename R> __device__ __forceinline__ Cx<R> csub(Cx<R> a, Cx<R> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename R> __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
@@ -1017,11 +1022,12 @@ __global__ __launch_bounds__(kBlock) void k_fft_y(Cx<R> *data, int ln, int linne
 // energy += w_x g |rho^|^2 (w_x = 2 for kx > 0: the mirrored half),
 // field spectra E^_d = -i k_d g rho^ (d = x,y,z) and psi^ = g rho^, each
 // transformed back along z and written to fspec[d].  The nf field pencils
-// are transformed as one batch of nfp (nf or 1) at a time.
+// (field ids fbase .. fbase+nf-1, id 3 = psi) are transformed as batches of
+// nfp (nf or 1) at a time.
 // tab: s_x (Mx/2), s_y (My), s_z (Mz), k_x (Mx/2), k_y (My), k_z (Mz).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec,
-                                                    Geom g, int lnz, int lhx, int lnb, int nf, int nfp,
+                                                    Geom g, int lnz, int lhx, int lnb, int nf, int nfp, int fbase,
                                                     const Cx<R> *__restrict__ tw_z, const R *__restrict__ sx,
                                                     const R *__restrict__ sy, const R *__restrict__ sz,
                                                     const R *__restrict__ kvx, const R *__restrict__ kvy,
@@ -1055,7 +1061,7 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
         lnz, lnb, nfp, tw_z, X, Y, nb,
         [=](int o, int i, int f) {
           const Cx<R> v = S[i * nb + f];
-          const int c = o0 + o;
+          const int c = fbase + o0 + o;
           if (c == 3) return v;
           const int pidx = (int)p0 + f;
           const R kd = c == 0 ? kvx[pidx & (hx - 1)] : (c == 1 ? kvy[pidx >> lhx] : kvz[i]);
@@ -1069,12 +1075,13 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
 }
 
 // x pass, inverse, nf components: bins 0 .. Mx/2-1 of each field (Nyquist
-// bin zero) -> Mx reals, written interleaved as real4 (E_x, E_y, E_z, psi).
+// bin zero) -> Mx reals, written interleaved as real4 (E_x, E_y, E_z, psi),
+// or, for a single field (SCALAR), as a plain real grid.
 // Z_k = (X_k + conj X_{n-k}) + i e^{+2 pi i k/Mx} (X_k - conj X_{n-k}),
 // z = inverse transform (length n), x_{2j} = Re z_j, x_{2j+1} = Im z_j.
 // The untangling is folded into the first stage's loads.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__ fspec, real4<R> *__restrict__ field,
+template <typename R, bool SCALAR>
+__global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__ fspec, void *__restrict__ field_out,
                                                        Geom g, int lnh, int lnb, int nf,
                                                        const Cx<R> *__restrict__ tw_n,
                                                        const Cx<R> *__restrict__ tw_2n) {
@@ -1103,7 +1110,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__
       },
       [=](int o, int i, int f, Cx<R> v) { res[(o * n + i) * ldp + f] = v; });
   __syncthreads();
-  real4<R> *dst = field + row0 * Mx;
+  if constexpr (SCALAR) {
+    // one field: a plain real grid
+    R *dst = reinterpret_cast<R *>(field_out) + row0 * Mx;
+    for (int e = threadIdx.x; e < (nb * Mx); e += blockDim.x) {
+      const int xi = e & (Mx - 1), f = e >> (lnh + 1);
+      const Cx<R> v = res[(xi >> 1) * ldp + f];
+      dst[e] = (xi & 1) ? v.y : v.x;
+    }
+    return;
+  }
+  real4<R> *dst = reinterpret_cast<real4<R> *>(field_out) + row0 * Mx;
   for (int e = threadIdx.x; e < (nb * Mx); e += blockDim.x) {
     const int xi = e & (Mx - 1), f = e >> (lnh + 1);
     const int j = xi >> 1;
@@ -1134,12 +1151,13 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__
 // GRAD: exact gradient of the discrete energy instead,
 //   dE/dr_i,d = pref q_i (M_d/L_d) sum_l dB/ds_d psi_l,  dE/dq_i = phi_i.
 // --------------------------------------------------------------------------
-template <typename R, int P, bool GRAD>
+template <typename R, int P, bool GRAD, typename FT>
 __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restrict__ part,
                                                          const int *__restrict__ perm,
                                                          const int *__restrict__ counts, Geom g,
-                                                         const real4<R> *__restrict__ field, R pref, R gscale,
-                                                         R *__restrict__ vec_out, R *__restrict__ sca_out) {
+                                                         const FT *__restrict__ field, R pref, R gscale,
+                                                         R sscale, R *__restrict__ vec_out,
+                                                         R *__restrict__ sca_out) {
   // per-thread y/z weights live in LDS so the (z, y) row loop can stay rolled
   // without indexing registers dynamically; only the x sweep is unrolled
   __shared__ R wsh[kGatherBlock][GRAD ? 4 : 2][P];
@@ -1180,8 +1198,8 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
     const int jz = r / P, jy = r - jz * P;
     const int gz = wrapi(b[2] + jz, g.M[2]);
     const int gy = wrapi(b[1] + jy, g.M[1]);
-    const real4<R> *row = field + ((size_t)gz * g.M[1] + gy) * g.M[0];
-    if (!GRAD) {
+    const FT *row = field + ((size_t)gz * g.M[1] + gy) * g.M[0];
+    if constexpr (!GRAD) {
       const R wzy = ws[1][jz] * ws[0][jy];
 #pragma unroll
       for (int jx = 0; jx < P; ++jx) {
@@ -1197,7 +1215,7 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
       const R wzy = wz_ * wy_, dzy = dz_ * wy_, wzdy = wz_ * dy_;
 #pragma unroll
       for (int jx = 0; jx < P; ++jx) {
-        const R psi = row[gx[jx]].w;
+        const R psi = psi_of<R>(row[gx[jx]]);
         a0 += wzy * dx[jx] * psi;
         a1 += wzdy * wx[jx] * psi;
         a2 += dzy * wx[jx] * psi;
@@ -1221,7 +1239,7 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
       vec_out[3 * i + 1] = c * R(g.M[1] / g.L[1]) * a1;
       vec_out[3 * i + 2] = c * R(g.M[2] / g.L[2]) * a2;
     }
-    if (sca_out) sca_out[i] = gscale * pref * a3;
+    if (sca_out) sca_out[i] = sscale * pref * a3;
   }
 }
 
@@ -1229,15 +1247,15 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
 // fields plus the (P-1)-point halo in LDS with coalesced row loads, then
 // interpolates every active particle of the tile from LDS.  Used when the
 // staged tile fits the LDS budget; same outputs as k_gather.
-template <typename R, int P, bool GRAD>
+template <typename R, int P, bool GRAD, typename FT>
 __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
                                                                   const int *__restrict__ perm,
                                                                   const int *__restrict__ off_t, Geom g,
-                                                                  const real4<R> *__restrict__ field, R pref,
-                                                                  R gscale, R *__restrict__ vec_out,
+                                                                  const FT *__restrict__ field, R pref,
+                                                                  R gscale, R sscale, R *__restrict__ vec_out,
                                                                   R *__restrict__ sca_out) {
   extern __shared__ unsigned char smem_raw[];
-  real4<R> *ext = reinterpret_cast<real4<R> *>(smem_raw);
+  FT *ext = reinterpret_cast<FT *>(smem_raw);
   const int tid = threadIdx.x;
   int t = blockIdx.x;
   const int tx = t % g.nt[0];
@@ -1276,14 +1294,14 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       if (GRAD) bspline_d<R, P>(v.z - fl, wz, dz); else bspline<R, P>(v.z - fl, wz);
     }
     R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
-    const real4<R> *base = ext + (l[2] * E1 + l[1]) * E0 + l[0];
+    const FT *base = ext + (l[2] * E1 + l[1]) * E0 + l[0];
     // rolled (z, y) row loop: the row index is uniform across the wave, so
     // the weight arrays are indexed without spilling them
 #pragma unroll 1
     for (int r = 0; r < P * P; ++r) {
       const int jz = r / P, jy = r - jz * P;
-      const real4<R> *row = base + (jz * E1 + jy) * E0;
-      if (!GRAD) {
+      const FT *row = base + (jz * E1 + jy) * E0;
+      if constexpr (!GRAD) {
         const R wzy = wz[jz] * wy[jy];
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
@@ -1298,7 +1316,7 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
         const R wzy = wz[jz] * wy[jy], dzy = dz[jz] * wy[jy], wzdy = wz[jz] * dy[jy];
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
-          const R psi = row[jx].w;
+          const R psi = psi_of<R>(row[jx]);
           a0s += wzy * dx[jx] * psi;
           a1s += wzdy * wx[jx] * psi;
           a2s += dzy * wx[jx] * psi;
@@ -1322,7 +1340,7 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
         vec_out[3 * i + 1] = c * R(g.M[1] / g.L[1]) * a1s;
         vec_out[3 * i + 2] = c * R(g.M[2] / g.L[2]) * a2s;
       }
-      if (sca_out) sca_out[i] = gscale * pref * a3s;
+      if (sca_out) sca_out[i] = sscale * pref * a3s;
     }
   }
 }
@@ -1705,7 +1723,7 @@ static FftPlan fft_plan(const Geom &g, size_t cs, int nf) {
 
 int nblk_z(const Geom &g, bool fp64) {
   const size_t cs = fp64 ? 16 : 8;
-  return std::max(fft_plan(g, cs, 3).zblocks, fft_plan(g, cs, 4).zblocks);
+  return std::max(fft_plan(g, cs, 1).zblocks, std::max(fft_plan(g, cs, 3).zblocks, fft_plan(g, cs, 4).zblocks));
 }
 
 // table layout (in reals): [0] tw x-half (n=Mx/2) complex, [1] tw e^{-2pi i k/Mx}
@@ -1774,32 +1792,34 @@ static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
     hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(spread_block<R>()), 0, st,
                        (const real4<R> *)w.part_t, w.off_t, (const int *)w.runs, w.nruns, g, (R *)w.grid);
 }
-template <typename R, int P>
+template <typename FT, int P>
 static size_t gather_tile_lds(const Geom &g) {
-  return (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1) * sizeof(real4<R>);
+  return (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1) * sizeof(FT);
 }
-template <typename R, int P>
-static void launch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R *vo, R *so,
-                          bool grad) {
-  const size_t lds = gather_tile_lds<R, P>(g);
+// Gather kinds: ik forces and potentials from the interleaved (E, psi) grid;
+// gradient form (forces -dE/dr or the adjoint dE/dr, scaled by gs, and the
+// potential scaled by ss) from psi, read either from the interleaved grid
+// (.w) or from a potential-only grid (scalar).
+enum GatherKind { kGatherIk = 0, kGatherGrad4 = 1, kGatherGradScalar = 2 };
+template <typename R, int P, bool GRAD, typename FT>
+static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R ss, R *vo, R *so) {
+  const size_t lds = gather_tile_lds<FT, P>(g);
   if (lds <= 65536) {
-    if (grad)
-      hipLaunchKernelGGL((k_gather_tile<R, P, true>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
-                         (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const real4<R> *)w.field, pref, gs,
-                         vo, so);
-    else
-      hipLaunchKernelGGL((k_gather_tile<R, P, false>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
-                         (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const real4<R> *)w.field, pref, gs,
-                         vo, so);
+    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
+                       (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
+                       so);
     return;
   }
   const int nb = (g.n + kGatherBlock - 1) / kGatherBlock;
-  if (grad)
-    hipLaunchKernelGGL((k_gather<R, P, true>), dim3(nb), dim3(kGatherBlock), 0, st, (const real4<R> *)w.part_t,
-                       w.perm_t, w.counts, g, (const real4<R> *)w.field, pref, gs, vo, so);
-  else
-    hipLaunchKernelGGL((k_gather<R, P, false>), dim3(nb), dim3(kGatherBlock), 0, st, (const real4<R> *)w.part_t,
-                       w.perm_t, w.counts, g, (const real4<R> *)w.field, pref, gs, vo, so);
+  hipLaunchKernelGGL((k_gather<R, P, GRAD, FT>), dim3(nb), dim3(kGatherBlock), 0, st, (const real4<R> *)w.part_t,
+                     w.perm_t, w.counts, g, (const FT *)w.field, pref, gs, ss, vo, so);
+}
+template <typename R, int P>
+static void launch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R ss, R *vo, R *so,
+                          int kind) {
+  if (kind == kGatherIk) launch_gather_as<R, P, false, real4<R>>(g, w, st, pref, gs, ss, vo, so);
+  else if (kind == kGatherGrad4) launch_gather_as<R, P, true, real4<R>>(g, w, st, pref, gs, ss, vo, so);
+  else launch_gather_as<R, P, true, R>(g, w, st, pref, gs, ss, vo, so);
 }
 
 template <typename R>
@@ -1812,18 +1832,19 @@ static void dispatch_spread(const Geom &g, const Work &w, hipStream_t st) {
   }
 }
 template <typename R>
-static void dispatch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R *vo, R *so, bool grad) {
+static void dispatch_gather(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R ss, R *vo, R *so,
+                            int kind) {
   switch (g.p) {
-    case 2: launch_gather<R, 2>(g, w, st, pref, gs, vo, so, grad); break;
-    case 4: launch_gather<R, 4>(g, w, st, pref, gs, vo, so, grad); break;
-    case 6: launch_gather<R, 6>(g, w, st, pref, gs, vo, so, grad); break;
-    default: launch_gather<R, 8>(g, w, st, pref, gs, vo, so, grad); break;
+    case 2: launch_gather<R, 2>(g, w, st, pref, gs, ss, vo, so, kind); break;
+    case 4: launch_gather<R, 4>(g, w, st, pref, gs, ss, vo, so, kind); break;
+    case 6: launch_gather<R, 6>(g, w, st, pref, gs, ss, vo, so, kind); break;
+    default: launch_gather<R, 8>(g, w, st, pref, gs, ss, vo, so, kind); break;
   }
 }
 
 template <typename R>
 hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R *x, const R *q, double *E,
-                          R *F, R *phi, bool all_active, bool want_psi, hipEvent_t *ev) {
+                          R *F, R *phi, bool all_active, bool want_psi, bool analytic, hipEvent_t *ev) {
   const size_t cs = sizeof(Cx<R>);
   const R *tab = (const R *)w.tables;
   const Cx<R> *tw_xh = (const Cx<R> *)(tab + w.tab_off[0]);
@@ -1834,9 +1855,12 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   const R *kvx = tab + w.tab_off[7], *kvy = tab + w.tab_off[8], *kvz = tab + w.tab_off[9];
   const int hx = g.M[0] / 2;
   const size_t halfG = (size_t)hx * g.M[1] * g.M[2];
-  // the potential field psi is transformed only when potentials (or a later
-  // adjoint) need it; forces use the three ik fields
-  const int nfield = want_psi ? 4 : 3;
+  // ik forces use the three field spectra, and the potential field psi is
+  // transformed only when potentials (or a later adjoint) need it; the
+  // analytic-derivative mode transforms psi alone and differentiates the
+  // window in the gather
+  const int nfield = analytic ? 1 : (want_psi ? 4 : 3);
+  const int fbase = analytic ? 3 : 0;
   const FftPlan P = fft_plan(g, cs, nfield);
   auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
 
@@ -1877,21 +1901,28 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   mark(4);
   // z fused: forward z, influence, energy, inverse z of the field spectra
   hipLaunchKernelGGL((k_z_fused<R>), dim3(P.zblocks), dim3(kBlock), P.lds_z, st, (const Cx<R> *)w.spec,
-                     (Cx<R> *)w.fspec, g, P.lnz, P.lhx, P.lb_z, nfield, P.nfp, tw_z, sx, sy, sz, kvx, kvy, kvz,
-                     w.kpart);
+                     (Cx<R> *)w.fspec, g, P.lnz, P.lhx, P.lb_z, nfield, P.nfp, fbase, tw_z, sx, sy, sz, kvx, kvy,
+                     kvz, w.kpart);
   ENUF_TRY(hipGetLastError());
   mark(5);
   // inverse y (nfield components), inverse x c2r -> interleaved fields
   hipLaunchKernelGGL((k_fft_y<R, 1>), dim3(hx >> P.lb_y, g.M[2], nfield), dim3(kBlock), P.lds_y, st,
                      (Cx<R> *)w.fspec, P.lny, P.lhx, (size_t)hx * g.M[1], halfG, tw_y, P.lb_y);
-  hipLaunchKernelGGL((k_fft_x_c2r4<R>), dim3((g.M[1] * g.M[2]) >> P.lb_c2r), dim3(kBlock), P.lds_c2r, st,
-                     (const Cx<R> *)w.fspec, (real4<R> *)w.field, g, P.lnh, P.lb_c2r, nfield, tw_xh, tw_x2);
+  if (analytic)
+    hipLaunchKernelGGL((k_fft_x_c2r4<R, true>), dim3((g.M[1] * g.M[2]) >> P.lb_c2r), dim3(kBlock), P.lds_c2r, st,
+                       (const Cx<R> *)w.fspec, w.field, g, P.lnh, P.lb_c2r, nfield, tw_xh, tw_x2);
+  else
+    hipLaunchKernelGGL((k_fft_x_c2r4<R, false>), dim3((g.M[1] * g.M[2]) >> P.lb_c2r), dim3(kBlock), P.lds_c2r,
+                       st, (const Cx<R> *)w.fspec, w.field, g, P.lnh, P.lb_c2r, nfield, tw_xh, tw_x2);
   ENUF_TRY(hipGetLastError());
   mark(6);
   // gather
   const double V = g.L[0] * g.L[1] * g.L[2];
   const R pref = (R)(g.ke * 4.0 * 3.14159265358979323846 / V);
-  if (F || phi) dispatch_gather<R>(g, w, st, pref, R(1), F, phi, false);
+  if (F || phi) {
+    if (analytic) dispatch_gather<R>(g, w, st, pref, R(-1), R(1), F, phi, kGatherGradScalar);
+    else dispatch_gather<R>(g, w, st, pref, R(1), R(1), F, phi, kGatherIk);
+  }
   ENUF_TRY(hipGetLastError());
   mark(7);
   // pair
@@ -1911,13 +1942,15 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
 }
 
 template <typename R>
-hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double gscale, R *dEdx, R *dEdq) {
+hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double gscale, R *dEdx, R *dEdq,
+                          bool psi_scalar) {
   if (dEdx) hipLaunchKernelGGL((k_fill_real<R>), dim3(256), dim3(kBlock), 0, st, dEdx, 3LL * g.n);
   if (dEdq) hipLaunchKernelGGL((k_fill_real<R>), dim3(256), dim3(kBlock), 0, st, dEdq, (long long)g.n);
   ENUF_TRY(hipGetLastError());
   const double V = g.L[0] * g.L[1] * g.L[2];
   const R pref = (R)(g.ke * 4.0 * 3.14159265358979323846 / V);
-  dispatch_gather<R>(g, w, st, pref, (R)gscale, dEdx, dEdq, true);
+  dispatch_gather<R>(g, w, st, pref, (R)gscale, (R)gscale, dEdx, dEdq,
+                     psi_scalar ? kGatherGradScalar : kGatherGrad4);
   ENUF_TRY(hipGetLastError());
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 1, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
@@ -1929,10 +1962,12 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
 }
 
 template hipError_t launch_forward<float>(const Geom &, const Work &, hipStream_t, const float *, const float *,
-                                          double *, float *, float *, bool, bool, hipEvent_t *);
+                                          double *, float *, float *, bool, bool, bool, hipEvent_t *);
 template hipError_t launch_forward<double>(const Geom &, const Work &, hipStream_t, const double *,
-                                           const double *, double *, double *, double *, bool, bool, hipEvent_t *);
-template hipError_t launch_adjoint<float>(const Geom &, const Work &, hipStream_t, double, float *, float *);
-template hipError_t launch_adjoint<double>(const Geom &, const Work &, hipStream_t, double, double *, double *);
+                                           const double *, double *, double *, double *, bool, bool, bool,
+                                           hipEvent_t *);
+template hipError_t launch_adjoint<float>(const Geom &, const Work &, hipStream_t, double, float *, float *, bool);
+template hipError_t launch_adjoint<double>(const Geom &, const Work &, hipStream_t, double, double *, double *,
+                                           bool);
 
 }  // namespace enuf

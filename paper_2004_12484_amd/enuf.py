@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libenuf.so")
 
 ENUF_OK, ENUF_EINVAL, ENUF_ENOMEM, ENUF_EDEVICE, ENUF_ENONFINITE, ENUF_ESTATE, ENUF_EUNSUPPORTED = range(7)
 ENUF_FP64, ENUF_FP32 = 0, 1
-OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK = 0, 1, 2, 3
+OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE = 0, 1, 2, 3, 4
+FORCE_MODES = {"ik": 0, "analytic": 1}
 STAGE_GRID, STAGE_SPECTRUM, STAGE_FIELDS, STAGE_SORTED, STAGE_COUNTS, STAGE_CELLS = range(6)
 PHASES = ("prep", "sort", "spread", "fft_fwd", "influence_z", "fft_inv", "gather", "pair", "finalize")
 
@@ -88,7 +89,8 @@ class Enuf:
     (precision "f64") or float32 ("f32"); energies are always float64.
     """
 
-    def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False):
+    def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False,
+                 force_mode="ik"):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("ENUF needs a HIP GPU; torch.cuda.is_available() is False")
@@ -116,6 +118,9 @@ class Enuf:
             self.set_option(OPT_KE, ke)
         if check:
             self.set_option(OPT_CHECK, 1)
+        self.force_mode = force_mode
+        if force_mode != "ik":
+            self.set_option(OPT_FORCE_MODE, FORCE_MODES[force_mode])
         self._E = torch.zeros(5, dtype=torch.float64, device=self.device)
 
     # -- plumbing ---------------------------------------------------------

@@ -137,12 +137,14 @@ def charged_fluid(N: int = 1 << 20, L: float = 70.0, charged_fraction: float = 0
                     (M, M, M), p, precision, seed)
 
 
-def ions_1m(N: int = 1 << 20, L: float = 70.0, seed: int = 3, r_c: float = 2.1, alpha: float = 2.9 / 2.1,
-            M: int = 256, p: int = 4, precision: str = "f32") -> Workload:
+def ions_1m(N: int = 1 << 20, L: float = 70.0, seed: int = 3, r_c: float = 1.8, alpha: float = 2.9 / 1.8,
+            M: int = 256, p: int = 6, precision: str = "f32") -> Workload:
     """One million ions: the charged-fluid geometry (uniform positions, same
     seed) with every bead charged, half +1 and half -1 by a seeded
     permutation.  The default (alpha, r_c, M, p) is the fastest FP32 setting
-    of a grid search whose RMS force error against the oracle is <= 1e-4."""
+    of a timed grid search (both force modes) whose RMS force error against
+    the oracle is <= 1e-4 with margin; it is meant for the analytic-derivative
+    force mode."""
     box = np.array([L, L, L], float)
     rng = np.random.default_rng(seed)
     x = rng.uniform(0.0, 1.0, size=(N, 3)) * box[None, :]

@@ -61,6 +61,16 @@ def _run(x, q, box, alpha, rc, M, p, prec, reps=2):
     return F, best[0], best[1]
 
 
+def reference_setting(N, box):
+    """The tight FP64 setting the sweep errors are measured against:
+    alpha r_c = 4.2 (erfc ~ 3e-9), alpha h <= 0.35, p = 8."""
+    box = np.asarray(box, float)
+    a = spacing(N, box)
+    rc_ref = min(0.499 * float(box.min()), 3.5 * a)
+    alpha_ref = ALPHA_RC_CONV / rc_ref
+    return {"alpha": alpha_ref, "r_c": rc_ref, "M": grid_for(alpha_ref, box, ALPHA_H_CONV), "p": 8}
+
+
 def sweep_system(seed):
     w = inputs.random_system(seed)
     box = np.asarray(w.box, float)
@@ -73,11 +83,8 @@ def sweep_system(seed):
     x32 = x64.float()
     q32 = q64.float()
     charged = torch.tensor(w.q != 0, device=dev)
-    # tight reference
-    rc_ref = min(0.499 * lmin, 3.5 * a)
-    alpha_ref = ALPHA_RC_CONV / rc_ref
-    M_ref = grid_for(alpha_ref, box, ALPHA_H_CONV)
-    F_ref, t_ref, _ = _run(x64, q64, box, alpha_ref, rc_ref, M_ref, 8, "f64", reps=1)
+    ref = reference_setting(N, box)
+    F_ref, t_ref, _ = _run(x64, q64, box, ref["alpha"], ref["r_c"], ref["M"], ref["p"], "f64", reps=1)
     Fr = F_ref[charged]
     nref = torch.linalg.norm(Fr)
 

@@ -81,7 +81,7 @@ def evaluate(paths, out, max_systems=200, log=print):
     import torch
 
     from . import enuf, inputs
-    from .sweep import ALPHA_H_CONV, ALPHA_RC_CONV, grid_for
+    from .sweep import reference_setting
 
     recs = [r for r in load_sweeps(paths) if r["seed"] % 10 == 0][:max_systems]
     pred = P.Predictor()
@@ -90,14 +90,12 @@ def evaluate(paths, out, max_systems=200, log=print):
     for r in recs:
         w = inputs.random_system(r["seed"])
         box = np.asarray(w.box, float)
-        a = P.spacing(w.N, box)
         x64 = torch.tensor(w.x, dtype=torch.float64, device=dev)
         q64 = torch.tensor(w.q, dtype=torch.float64, device=dev)
         x32, q32 = x64.float(), q64.float()
         charged = torch.tensor(w.q != 0, device=dev)
-        rc_ref = min(0.499 * box.min(), 3.5 * a)
-        aref = ALPHA_RC_CONV / rc_ref
-        eng = enuf.Enuf(box, w.N, aref, rc_ref, grid_for(aref, box, ALPHA_H_CONV), 8, precision="f64")
+        ref = reference_setting(w.N, box)
+        eng = enuf.Enuf(box, w.N, ref["alpha"], ref["r_c"], ref["M"], ref["p"], precision="f64")
         _, Fref, _ = eng.energy_forces(x64, q64)
         eng.close()
         Fr = Fref[charged]
