@@ -67,6 +67,43 @@ def algorithmic_bytes(w, rs, nq, nfield=3):
     }
 
 
+# phase -> kernel of that phase whose counters profiles/traffic_<workload>.json holds
+PHASE_KERNEL = {"pair": "k_pair", "gather": "k_gather_tile", "spread": "k_spread_mfma"}
+
+
+def sources_sha():
+    """Hash of the library sources: counter bytes are reported only for the
+    build they were measured on."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2004_12484_amd", "csrc", "*"))
+                   + glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, phase):
+    """HBM bytes per launch of the phase's kernel from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counters (each scaled by what the counter reads for a plain
+    copy of known size), if they were taken on this exact build."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path) or phase not in PHASE_KERNEL:
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("sources_sha") != sources_sha():
+        return None
+    k = t["kernels"].get(PHASE_KERNEL[phase])
+    if k is None:
+        return None
+    return 1024.0 * (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"])
+
+
 def pair_count(w, nq):
     """Expected number of (ordered) charged pairs inside r_c for a uniform fluid."""
     V = float(np.prod(w.box))
@@ -289,13 +326,15 @@ def main():
     if dom in ab:
         achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": ab[dom]}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, dom),
+                "bytes_per_launch": ab[dom]}
     else:
         pairs = pair_count(w, nq)
         peak = FP32_VALU_TFLOPS if rs == 4 else FP64_VALU_TFLOPS
         achieved = pairs * PAIR_FLOPS / (phases[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "flops_per_launch": pairs * PAIR_FLOPS}
+                "frac": achieved / peak, "traffic": measured_traffic(w.name, dom),
+                "flops_per_launch": pairs * PAIR_FLOPS}
     hbm = {k: ab[k] / (phases[k] * 1e-3) / 1e9 for k in ab}
 
     rec = {
