@@ -34,6 +34,15 @@ template <typename R> using real4 = typename V4<R>::T;
 
 template <typename R> struct Cx { R x, y; };
 
+// plain register types for staging copies (no constructors, so arrays of
+// them stay in registers)
+template <typename T> struct PodOf { using type = T; };
+template <> struct PodOf<float4> { using type = float __attribute__((ext_vector_type(4))); };
+template <> struct PodOf<double4> { using type = double __attribute__((ext_vector_type(4))); };
+template <> struct PodOf<Cx<float>> { using type = float __attribute__((ext_vector_type(2))); };
+template <> struct PodOf<Cx<double>> { using type = double __attribute__((ext_vector_type(2))); };
+template <typename T> using pod_t = typename PodOf<T>::type;
+
 // the potential component of a field grid point: .w of the interleaved
 // (E_x, E_y, E_z, psi) layout, or the value itself on a potential-only grid
 template <typename R> __device__ __forceinline__ R psi_of(const real4<R> &f) { return f.w; }
@@ -981,7 +990,21 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_r2c(const R *__restrict__ grid
   Cx<R> *B1 = B0 + n * ldp;
   const size_t row0 = (size_t)blockIdx.x * nb;
   const Cx<R> *src = reinterpret_cast<const Cx<R> *>(grid) + (row0 << lnh);
-  for (int e = threadIdx.x; e < (n << lnb); e += blockDim.x) B0[(e & (n - 1)) * ldp + (e >> lnh)] = src[e];
+  for (int e0 = threadIdx.x; e0 < (n << lnb); e0 += 4 * blockDim.x) {
+    using V = pod_t<Cx<R>>;
+    V v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = e0 + k * blockDim.x;
+      v[k] = V{};
+      if (e < (n << lnb)) v[k] = reinterpret_cast<const V *>(src)[e];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = e0 + k * blockDim.x;
+      if (e < (n << lnb)) reinterpret_cast<V *>(B0)[(e & (n - 1)) * ldp + (e >> lnh)] = v[k];
+    }
+  }
   __syncthreads();
   Cx<R> *res = (fft_nstages(lnh) & 1) ? B1 : B0;
   fft_run<R, -1>(lnh, lnb, 1, tw_n, B1, B0, ldp, [=](int, int i, int f) { return B0[i * ldp + f]; },
@@ -1092,10 +1115,28 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__
   Cx<R> *B0 = reinterpret_cast<Cx<R> *>(smem_raw);
   Cx<R> *B1 = B0 + nf * n * ldp;
   const size_t row0 = (size_t)blockIdx.x * nb;
-  for (int e = threadIdx.x; e < ((nf * n) << lnb); e += blockDim.x) {
-    const int k = e & (n - 1), t = e >> lnh;
-    const int f = t & (nb - 1), o = t >> lnb;
-    B0[(o * n + k) * ldp + f] = fspec[o * half + ((row0 + f) << lnh) + k];
+  for (int e0 = threadIdx.x; e0 < ((nf * n) << lnb); e0 += 4 * blockDim.x) {
+    using V = pod_t<Cx<R>>;
+    V v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * blockDim.x;
+      v[u] = V{};
+      if (e < ((nf * n) << lnb)) {
+        const int k = e & (n - 1), t = e >> lnh;
+        const int f = t & (nb - 1), o = t >> lnb;
+        v[u] = reinterpret_cast<const V *>(fspec)[o * half + ((row0 + f) << lnh) + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < ((nf * n) << lnb)) {
+        const int k = e & (n - 1), t = e >> lnh;
+        const int f = t & (nb - 1), o = t >> lnb;
+        reinterpret_cast<V *>(B0)[(o * n + k) * ldp + f] = v[u];
+      }
+    }
   }
   __syncthreads();
   Cx<R> *res = (fft_nstages(lnh) & 1) ? B1 : B0;
@@ -1244,9 +1285,27 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
 }
 
 // Tile form of the gather: one workgroup per grid tile stages the tile's
-// fields plus the (P-1)-point halo in LDS with coalesced row loads, then
-// interpolates every active particle of the tile from LDS.  Used when the
-// staged tile fits the LDS budget; same outputs as k_gather.
+// fields plus the (P-1)-point halo in LDS, one 32-lane group per contiguous
+// x row (E0 <= 32 points), then interpolates every active particle of the
+// tile from LDS.  Four lanes share a particle: each sums the (z, y) rows of
+// one parity pair (z even/odd x y even/odd; P is even) and the four partial
+// sums are combined with lane shuffles, so a tile of 64 particles keeps all
+// 256 lanes busy.  Used when
+// the staged tile fits the LDS budget; same outputs as k_gather.
+constexpr int kGatherLanes = 4;  // lanes per particle in k_gather_tile
+
+// b ? y : x as a bit blend, so that picking between two register values is
+// never turned into an indexed load from a stack copy of the array
+__device__ __forceinline__ float pick(int b, float x, float y) {
+  const unsigned m = 0u - (unsigned)b;
+  return __uint_as_float((__float_as_uint(x) & ~m) | (__float_as_uint(y) & m));
+}
+__device__ __forceinline__ double pick(int b, double x, double y) {
+  const unsigned long long m = 0ull - (unsigned long long)b;
+  return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(x) & ~m) |
+                                          ((unsigned long long)__double_as_longlong(y) & m)));
+}
+
 template <typename R, int P, bool GRAD, typename FT>
 __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
                                                                   const int *__restrict__ perm,
@@ -1266,20 +1325,48 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
   const int E0 = g.T[0] + P - 1, E1 = g.T[1] + P - 1, E2 = g.T[2] + P - 1;
   const int e0x = t0[0] - P / 2 + 1, e0y = t0[1] - P / 2 + 1, e0z = t0[2] - P / 2 + 1;
   const int nrow = E1 * E2;
-  // one thread per (row, x) with the rows of E0 points loaded contiguously
-  for (int e = tid; e < nrow * E0; e += blockDim.x) {
-    const int ix = e % E0;
-    const int r = e / E0;
-    const int iy = r % E1;
-    const int iz = r / E1;
-    const int gx = wrapi(e0x + ix, g.M[0]), gy = wrapi(e0y + iy, g.M[1]), gz = wrapi(e0z + iz, g.M[2]);
-    ext[e] = field[((size_t)gz * g.M[1] + gy) * g.M[0] + gx];
+  {
+    // rows (iy, iz) of E0 contiguous points: lane ix of a 32-lane group;
+    // eight rows' loads are issued before any is written to LDS
+    constexpr int kB = 8;
+    const int ix = tid & 31;
+    const int gx = wrapi(e0x + ix, g.M[0]);
+    const float inv_e1 = 1.0f / (float)E1;
+    const int step = blockDim.x >> 5;
+    for (int r0 = tid >> 5; r0 < nrow; r0 += kB * step) {
+      using V = pod_t<FT>;
+      const V *fsrc = reinterpret_cast<const V *>(field);
+      V *edst = reinterpret_cast<V *>(ext);
+      V v[kB];
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        const int r = r0 + k * step;
+        v[k] = V{};
+        if (r < nrow && ix < E0) {
+          const int iz = (int)(((float)r + 0.5f) * inv_e1);
+          const int iy = r - iz * E1;
+          const int gy = wrapi(e0y + iy, g.M[1]), gz = wrapi(e0z + iz, g.M[2]);
+          v[k] = fsrc[((size_t)gz * g.M[1] + gy) * g.M[0] + gx];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        const int r = r0 + k * step;
+        if (r < nrow && ix < E0) edst[r * E0 + ix] = v[k];
+      }
+    }
   }
   __syncthreads();
   const int tile = blockIdx.x;
   const int a0 = off_t[tile * kTileBins], a1 = off_t[tile * kTileBins + kTileBins];
-  for (int j = a0 + tid; j < a1; j += blockDim.x) {
-    const real4<R> v = part[j];
+  const int sub = tid & (kGatherLanes - 1);
+  // every lane of a wave runs the same number of iterations (the shuffles
+  // below need all four lanes of a particle); lanes past the end idle
+  const int npass = (a1 - a0 + (blockDim.x / kGatherLanes) - 1) / (blockDim.x / kGatherLanes);
+  for (int it = 0; it < npass; ++it) {
+    const int j = a0 + it * (blockDim.x / kGatherLanes) + (tid / kGatherLanes);
+    const bool live = j < a1;
+    const real4<R> v = part[live ? j : a0];
     int l[3];
     R wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
     {
@@ -1294,36 +1381,67 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       if (GRAD) bspline_d<R, P>(v.z - fl, wz, dz); else bspline<R, P>(v.z - fl, wz);
     }
     R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
-    const FT *base = ext + (l[2] * E1 + l[1]) * E0 + l[0];
-    // rolled (z, y) row loop: the row index is uniform across the wave, so
-    // the weight arrays are indexed without spilling them
-#pragma unroll 1
-    for (int r = 0; r < P * P; ++r) {
-      const int jz = r / P, jy = r - jz * P;
-      const FT *row = base + (jz * E1 + jy) * E0;
-      if constexpr (!GRAD) {
-        const R wzy = wz[jz] * wy[jy];
+    // this lane's (z, y) rows: z = za + 2m, y = yb + 2n (za, yb = the lane's
+    // bits), P^2/4 rows per lane; its z and y weights are picked once so the
+    // row loop indexes them statically
+    constexpr int H = P / 2;
+    const int za = sub >> 1, yb = sub & 1;
+    R mwz[H], mdz[H], mwy[H], mdy[H];
 #pragma unroll
-        for (int jx = 0; jx < P; ++jx) {
-          const real4<R> f = row[jx];
-          const R w = wzy * wx[jx];
-          a0s += w * f.x;
-          a1s += w * f.y;
-          a2s += w * f.z;
-          a3s += w * f.w;
-        }
-      } else {
-        const R wzy = wz[jz] * wy[jy], dzy = dz[jz] * wy[jy], wzdy = wz[jz] * dy[jy];
+    for (int m = 0; m < H; ++m) {
+      mwz[m] = pick(za, wz[2 * m], wz[2 * m + 1]);
+      mwy[m] = pick(yb, wy[2 * m], wy[2 * m + 1]);
+      if (GRAD) {
+        mdz[m] = pick(za, dz[2 * m], dz[2 * m + 1]);
+        mdy[m] = pick(yb, dy[2 * m], dy[2 * m + 1]);
+      }
+    }
+    const FT *base = ext + ((l[2] + za) * E1 + l[1] + yb) * E0 + l[0];
 #pragma unroll
-        for (int jx = 0; jx < P; ++jx) {
-          const R psi = psi_of<R>(row[jx]);
-          a0s += wzy * dx[jx] * psi;
-          a1s += wzdy * wx[jx] * psi;
-          a2s += dzy * wx[jx] * psi;
-          a3s += wzy * wx[jx] * psi;
+    for (int mz = 0; mz < H; ++mz) {
+#pragma unroll
+      for (int my = 0; my < H; ++my) {
+        const FT *row = base + (2 * mz * E1 + 2 * my) * E0;
+        // x sums of the row first, then the row's z-y weight
+        if constexpr (!GRAD) {
+          R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+          for (int jx = 0; jx < P; ++jx) {
+            const real4<R> f = row[jx];
+            s0 += wx[jx] * f.x;
+            s1 += wx[jx] * f.y;
+            s2 += wx[jx] * f.z;
+            s3 += wx[jx] * f.w;
+          }
+          const R wzy = mwz[mz] * mwy[my];
+          a0s += wzy * s0;
+          a1s += wzy * s1;
+          a2s += wzy * s2;
+          a3s += wzy * s3;
+        } else {
+          R sw = 0, sd = 0;
+#pragma unroll
+          for (int jx = 0; jx < P; ++jx) {
+            const R psi = psi_of<R>(row[jx]);
+            sw += wx[jx] * psi;
+            sd += dx[jx] * psi;
+          }
+          const R wzy = mwz[mz] * mwy[my];
+          a0s += wzy * sd;
+          a1s += (mwz[mz] * mdy[my]) * sw;
+          a2s += (mdz[mz] * mwy[my]) * sw;
+          a3s += wzy * sw;
         }
       }
     }
+#pragma unroll
+    for (int o = 1; o < kGatherLanes; o <<= 1) {
+      a0s += __shfl_xor(a0s, o, 64);
+      a1s += __shfl_xor(a1s, o, 64);
+      a2s += __shfl_xor(a2s, o, 64);
+      a3s += __shfl_xor(a3s, o, 64);
+    }
+    if (!live || sub != 0) continue;
     const int i = perm[j];
     const R qi = v.w;
     if (!GRAD) {
@@ -1500,18 +1618,34 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
       __syncthreads();
       // stage candidates c0 .. c0+nc-1: every thread finds the range of its
       // candidates by binary search, so all global loads are in flight at once
-      for (int k = tid; k < nc; k += blockDim.x) {
-        const int c = c0 + k;
-        int lo = 0, hi2 = 27;
-        while (hi2 - lo > 1) {
-          const int mid = (lo + hi2) >> 1;
-          if (rp[mid] <= c) lo = mid; else hi2 = mid;
+      // two candidates per thread per pass, both loads in flight together
+      for (int k0 = tid; k0 < nc; k0 += 2 * blockDim.x) {
+        real4<R> u[2];
+        int lo[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = k0 + h * blockDim.x;
+          lo[h] = 0;
+          if (k < nc) {
+            const int c = c0 + k;
+            int hi2 = 27;
+            while (hi2 - lo[h] > 1) {
+              const int mid = (lo[h] + hi2) >> 1;
+              if (rp[mid] <= c) lo[h] = mid; else hi2 = mid;
+            }
+            u[h] = part[rs[lo[h]] + (c - rp[lo[h]])];
+          }
         }
-        real4<R> u = part[rs[lo] + (c - rp[lo])];
-        u.x += rsh[lo][0];
-        u.y += rsh[lo][1];
-        u.z += rsh[lo][2];
-        cand[k] = u;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = k0 + h * blockDim.x;
+          if (k < nc) {
+            u[h].x += rsh[lo[h]][0];
+            u[h].y += rsh[lo[h]][1];
+            u[h].z += rsh[lo[h]][2];
+            cand[k] = u[h];
+          }
+        }
       }
       __syncthreads();
       {
