@@ -39,7 +39,12 @@ WORKLOADS = {
     "ions_1m": dict(gen="ions_1m", kw={}, force_mode="analytic"),
     "electrolyte": dict(gen="electrolyte", kw={}),
     "nacl": dict(gen="nacl", kw={}),
-    "anisotropic": dict(gen="anisotropic", kw={}),
+    # 4M sites in 120 x 120 x 240: parameters from the selector (the network,
+    # or a grid search over a sweep of the system when it lies outside the
+    # network's training range) at the FP32 form's accuracy bar 5e-4 (FP32
+    # rounding of the positions alone costs ~2.8e-4 here: chain beads come
+    # within a few hundredths of each other), forces and dE/dq
+    "anisotropic": dict(gen="anisotropic", kw={}, select=5e-4, potential=True),
 }
 
 
@@ -143,7 +148,7 @@ def cpu_baseline(w, budget_s=20.0):
     }
 
 
-def golden_check(w, F, E):
+def golden_check(w, F, E, phi=None):
     """RMS relative force error and relative energy error against stored oracle
     values for this workload (tests/golden/<workload>_oracle.npz), if present.
     Files holding only F_conv (the converged Ewald force, whatever splitting
@@ -167,6 +172,9 @@ def golden_check(w, F, E):
         out.setdefault("rms_force_err", out["rms_force_err_rc_converged"])
     if "E" in g.files:
         out["energy_rel_err"] = float(abs(E - float(g["E"])) / abs(float(g["E"])))
+    if phi is not None and "phi_conv" in g.files:
+        # dE/dq against the converged potentials
+        out["rms_dEdq_err"] = float(np.linalg.norm(phi[s] - g["phi_conv"]) / np.linalg.norm(g["phi_conv"]))
     return out
 
 
@@ -271,6 +279,14 @@ def main():
     if args.precision is not None:
         kw["precision"] = args.precision
     w = getattr(inputs, spec["gen"])(**kw)
+    selection = None
+    if spec.get("select") and args.alpha is None:
+        from paper_2004_12484_amd import params as P
+
+        pred = P.Predictor() if os.path.exists(P.MODEL_PATH) else None
+        s, selection = P.choose(w.x, w.q, w.box, spec["select"], predictor=pred)
+        w.alpha, w.r_c, w.M, w.p = s["alpha"], s["r_c"], tuple(s["M"]), s["p"]
+        selection["target"] = spec["select"]
     dt = torch.float64 if w.precision == "f64" else torch.float32
     rs = 8 if w.precision == "f64" else 4
     dev = torch.device("cuda", 0)
@@ -282,10 +298,12 @@ def main():
                     force_mode=force_mode)
     E = torch.empty(5, dtype=torch.float64, device=dev)
     F = torch.empty((w.N, 3), dtype=dt, device=dev)
+    phi = torch.empty(w.N, dtype=dt, device=dev) if spec.get("potential") else None
     lib = enuf.load_library()
 
     def step():
-        st = lib.enuf_energy_forces(eng._h, enuf._ptr(x), enuf._ptr(q), enuf._ptr(E), enuf._ptr(F), None)
+        st = lib.enuf_energy_forces(eng._h, enuf._ptr(x), enuf._ptr(q), enuf._ptr(E), enuf._ptr(F),
+                                    enuf._ptr(phi) if phi is not None else None)
         if st != 0:
             enuf._check(st, eng._h)
 
@@ -318,7 +336,7 @@ def main():
     nq = int(counts[1])
     Eh = E.cpu().numpy()
     Fh = F.double().cpu().numpy()
-    acc = golden_check(w, Fh, float(Eh[0]))
+    acc = golden_check(w, Fh, float(Eh[0]), phi.double().cpu().numpy() if phi is not None else None)
 
     # roofline of the dominant phase
     ab = algorithmic_bytes(w, rs, nq)
@@ -343,7 +361,7 @@ def main():
         "vs_baseline": None, "dtype": "f32" if rs == 4 else "f64", "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "n_charged": nq, "box": [float(b) for b in w.box],
                    "M": list(w.M), "p": w.p, "alpha": w.alpha, "r_c": w.r_c, "precision": w.precision,
-                   "force_mode": force_mode,
+                   "force_mode": force_mode, "potentials": phi is not None, "selection": selection,
                    "seed": w.seed, "parallelism": "single GPU"},
         "ns_per_particle": ms * 1e6 / w.N, "ns_per_charged": ms * 1e6 / max(nq, 1),
         "wall_s": wall, "phase_ms": phases, "phase_gbs": hbm,

@@ -1618,34 +1618,18 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
       __syncthreads();
       // stage candidates c0 .. c0+nc-1: every thread finds the range of its
       // candidates by binary search, so all global loads are in flight at once
-      // two candidates per thread per pass, both loads in flight together
-      for (int k0 = tid; k0 < nc; k0 += 2 * blockDim.x) {
-        real4<R> u[2];
-        int lo[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int k = k0 + h * blockDim.x;
-          lo[h] = 0;
-          if (k < nc) {
-            const int c = c0 + k;
-            int hi2 = 27;
-            while (hi2 - lo[h] > 1) {
-              const int mid = (lo[h] + hi2) >> 1;
-              if (rp[mid] <= c) lo[h] = mid; else hi2 = mid;
-            }
-            u[h] = part[rs[lo[h]] + (c - rp[lo[h]])];
-          }
+      for (int k = tid; k < nc; k += blockDim.x) {
+        const int c = c0 + k;
+        int lo = 0, hi2 = 27;
+        while (hi2 - lo > 1) {
+          const int mid = (lo + hi2) >> 1;
+          if (rp[mid] <= c) lo = mid; else hi2 = mid;
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int k = k0 + h * blockDim.x;
-          if (k < nc) {
-            u[h].x += rsh[lo[h]][0];
-            u[h].y += rsh[lo[h]][1];
-            u[h].z += rsh[lo[h]][2];
-            cand[k] = u[h];
-          }
-        }
+        real4<R> u = part[rs[lo] + (c - rp[lo])];
+        u.x += rsh[lo][0];
+        u.y += rsh[lo][1];
+        u.z += rsh[lo][2];
+        cand[k] = u;
       }
       __syncthreads();
       {
@@ -1718,9 +1702,19 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
 // energy parts in FP64: (total, E_R, E_K, E_self, E_bg)
 __global__ __launch_bounds__(1024) void k_finalize(const double *kpart, int nk, const double *rpart, int nr,
                                                   const double *scal, Geom g, double *E) {
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nk; i += blockDim.x) a += kpart[i];
-  for (int i = threadIdx.x; i < nr; i += blockDim.x) b += rpart[i];
+  // eight independent partial sums per thread keep eight loads in flight
+  auto sum = [](const double *v, int n) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * step < n; i += 8 * step) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += v[i + k * step];
+    }
+    for (; i < n; i += step) acc[0] += v[i];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  };
+  double a = sum(kpart, nk), b = sum(rpart, nr);
   a = block_sum(a);
   b = block_sum(b);
   if (threadIdx.x == 0) {

@@ -24,6 +24,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 MODEL_PATH = os.path.join(HERE, "data", "param_mlp.npz")
 P_CHOICES = (4, 6, 8)
 M_MIN, M_MAX = 8, 512
+# the systems the network was trained on (inputs.random_system): outside
+# these ranges its prediction is not used
+TRAIN_RANGE = {"N": (1000, 262144), "density": (0.1, 3.0), "f_q": (0.05, 1.0), "target": (3e-5, 1e-3)}
 
 
 def spacing(N, box):
@@ -90,6 +93,42 @@ class Predictor:
     def select(self, N, box, f_q, target):
         y = self.predict_raw(features(N, box, f_q, target))[0]
         return snap(box, N, y[0], y[1:4], y[4], y[5])
+
+
+def in_training_range(N, box, f_q, target):
+    box = np.asarray(box, float)
+    rho = N / float(np.prod(box))
+    aspect = sorted((box / box.min()).round(6))
+    ok_shape = aspect == [1.0, 1.0, 1.0] or aspect == [1.0, 1.0, 2.0]
+    r = TRAIN_RANGE
+    return (ok_shape and r["N"][0] <= N <= r["N"][1] and r["density"][0] <= rho <= r["density"][1]
+            and r["f_q"][0] <= f_q <= r["f_q"][1] and r["target"][0] <= target <= r["target"][1])
+
+
+def choose(x, q, box, target, predictor=None):
+    """Setting for one system: the network's prediction when the system lies
+    inside its training range, else (the fallback) a grid search over a sweep
+    of this very system.  Returns (setting, info)."""
+    import time
+
+    q = np.asarray(q)
+    N = len(q)
+    f_q = float(np.count_nonzero(q)) / N
+    if predictor is not None and in_training_range(N, box, f_q, target):
+        t0 = time.perf_counter()
+        s = predictor.select(N, box, f_q, target)
+        return s, {"method": "network", "select_ms": (time.perf_counter() - t0) * 1e3}
+    from .sweep import combine, sweep_arrays
+
+    t0 = time.perf_counter()
+    rec = sweep_arrays(x, q, box)
+    best = grid_search({"settings": combine(rec)}, target)
+    info = {"method": "grid_search", "select_ms": (time.perf_counter() - t0) * 1e3,
+            "search_gpu_ms": rec["cost_ms"], "settings_tried": int(len(rec["rows"]))}
+    if best is None:
+        raise RuntimeError("no swept setting meets the target")
+    info["expected_err"] = best["err"]
+    return {k: best[k] for k in ("alpha", "r_c", "M", "p")}, info
 
 
 def grid_search(sweep_row, target):

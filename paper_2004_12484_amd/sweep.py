@@ -28,7 +28,7 @@ import numpy as np
 import torch
 
 from . import enuf, inputs
-from .params import M_MAX, M_MIN, spacing
+from .params import M_MIN, spacing
 
 ALPHA_A = (0.7, 0.95, 1.2)          # alpha in units of 1/a
 ALPHA_RC = (2.5, 3.0, 3.5)          # alpha * r_c
@@ -38,8 +38,11 @@ ALPHA_RC_CONV = 4.2
 ALPHA_H_CONV = 0.35
 
 
+SWEEP_M_MAX = 1024  # the library's largest grid: large systems need it for the tight reference
+
+
 def pow2_ceil(v):
-    return int(min(M_MAX, max(M_MIN, 2 ** math.ceil(math.log2(max(v, 1.0))))))
+    return int(min(SWEEP_M_MAX, max(M_MIN, 2 ** math.ceil(math.log2(max(v, 1.0))))))
 
 
 def grid_for(alpha, box, ah):
@@ -71,22 +74,25 @@ def reference_setting(N, box):
     return {"alpha": alpha_ref, "r_c": rc_ref, "M": grid_for(alpha_ref, box, ALPHA_H_CONV), "p": 8}
 
 
-def sweep_system(seed):
-    w = inputs.random_system(seed)
-    box = np.asarray(w.box, float)
-    N = w.N
+def sweep_arrays(x, q, box):
+    """The separable sweep of one system given as arrays (positions [N,3],
+    charges [N], box [3]); returns the record `combine` takes."""
+    box = np.asarray(box, float)
+    q = np.asarray(q, float)
+    N = len(q)
     a = spacing(N, box)
     lmin = float(box.min())
     dev = torch.device("cuda", 0)
-    x64 = torch.tensor(w.x, dtype=torch.float64, device=dev)
-    q64 = torch.tensor(w.q, dtype=torch.float64, device=dev)
+    x64 = torch.tensor(np.asarray(x, float), dtype=torch.float64, device=dev)
+    q64 = torch.tensor(q, dtype=torch.float64, device=dev)
     x32 = x64.float()
     q32 = q64.float()
-    charged = torch.tensor(w.q != 0, device=dev)
+    charged = torch.tensor(q != 0, device=dev)
     ref = reference_setting(N, box)
     F_ref, t_ref, _ = _run(x64, q64, box, ref["alpha"], ref["r_c"], ref["M"], ref["p"], "f64", reps=1)
     Fr = F_ref[charged]
     nref = torch.linalg.norm(Fr)
+    del F_ref
 
     def err(F):
         return float((torch.linalg.norm(F.double()[charged] - Fr) / nref).item())
@@ -114,8 +120,15 @@ def sweep_system(seed):
                 F, t, tp = _run(x32, q32, box, alpha, rc_conv, M, p, "f32")
                 rows.append((alpha, rc_conv, *M, p, err(F), t, tp, 1))
                 cost += t
-    return {"seed": seed, "N": N, "box": box, "f_q": float(np.count_nonzero(w.q)) / N, "a": a,
+    return {"N": N, "box": box, "f_q": float(np.count_nonzero(q)) / N, "a": a,
             "rows": np.array(rows, float).reshape(-1, 10), "cost_ms": cost}
+
+
+def sweep_system(seed):
+    w = inputs.random_system(seed)
+    rec = sweep_arrays(w.x, w.q, w.box)
+    rec["seed"] = seed
+    return rec
 
 
 def combine(rec):

@@ -32,6 +32,7 @@ SPECS = {
 # erfc(alpha r) < 1e-10)
 FORCE_ONLY = {
     "ions_1m": (dict(), 512, 0.4, 1e-10),
+    "anisotropic": (dict(), 512, 0.4, 1e-10),
 }
 
 
@@ -42,11 +43,15 @@ def make_forces(name):
     sample = np.sort(np.random.default_rng(123).choice(charged, ns, replace=False))
     rc = min(0.5 * float(np.min(w.box)), 4.6 / alpha)
     t = time.time()
-    _, f_r, _ = ewald.real_minimage(w.x, w.q, w.box, alpha, rc, w.ke, sample=sample, energy=False)
-    _, f_k, _ = ewald.recip(w.x, w.q, w.box, alpha, w.ke, tol=tol, sample=sample)
+    _, f_r, p_r = ewald.real_minimage(w.x, w.q, w.box, alpha, rc, w.ke, sample=sample, energy=False)
+    _, f_k, p_k = ewald.recip(w.x, w.q, w.box, alpha, w.ke, tol=tol, sample=sample)
+    _, _, p_s, p_b = ewald.self_terms(w.q, w.box, alpha, w.ke)
     dt = time.time() - t
     path = os.path.join(HERE, f"{name}_oracle.npz")
-    np.savez_compressed(path, sample=sample.astype(np.int64), F_conv=f_r + f_k, alpha_oracle=alpha,
+    # potentials (dE/dq) are alpha-independent too once the self and
+    # background terms are included
+    np.savez_compressed(path, sample=sample.astype(np.int64), F_conv=f_r + f_k,
+                        phi_conv=p_r + p_k + p_s[sample] + p_b[sample], alpha_oracle=alpha,
                         rc_conv=rc, N=w.N, seed=w.seed, tol=tol)
     print(f"{name}: forces on {len(sample)} sampled ions, oracle {dt:.1f} s -> {path}", flush=True)
 
