@@ -152,18 +152,30 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   ok = ok && need(dalloc(c, (unsigned char **)&w.part_c, (size_t)n * 4 * rs));
   ok = ok && need(dalloc(c, &w.perm_t, (size_t)n));
   ok = ok && need(dalloc(c, &w.perm_c, (size_t)n));
+  const enuf::SortPlan sp = enuf::sort_plan(g, (int)rs);
+  const size_t nbk = (size_t)sp.nb[0] + sp.nb[1];
+  if (!enuf::fft_plans_fit(g, precision == ENUF_FP64)) {
+    delete c;
+    return fail(nullptr, ENUF_EUNSUPPORTED, "grid transform does not fit one workgroup's LDS");
+  }
+  if (nbk * sizeof(int) > 65536 || enuf::sort_stage_lds(sp, (int)rs) > 65536 || enuf::sort_fine_lds(sp) > 65536) {
+    delete c;
+    return fail(nullptr, ENUF_EUNSUPPORTED, "too many sort buckets for one workgroup's LDS");
+  }
   ok = ok && need(dalloc(c, &w.key_t, (size_t)n));
-  ok = ok && need(dalloc(c, &w.rank_t, (size_t)n));
   ok = ok && need(dalloc(c, &w.key_c, (size_t)n));
-  ok = ok && need(dalloc(c, &w.rank_c, (size_t)n));
-  ok = ok && need(dalloc(c, &w.off_t, (size_t)enuf::kTileBins * g.ntiles + 1));
-  ok = ok && need(dalloc(c, &w.bsum, (size_t)enuf::nblk_scan(g)));
-  ok = ok && need(dalloc(c, &w.bev, (size_t)enuf::nblk_scan(g)));
+  ok = ok && need(dalloc(c, &w.off_t, (size_t)sp.nbins[0] + 1));
+  ok = ok && need(dalloc(c, &w.off_c, (size_t)sp.nbins[1] + 1));
+  ok = ok && need(dalloc(c, &w.hist, (size_t)sp.nblk * nbk));
+  ok = ok && need(dalloc(c, &w.bbase, nbk + 2));
+  ok = ok && need(dalloc(c, (unsigned char **)&w.stg_t, (size_t)n * 4 * rs));
+  ok = ok && need(dalloc(c, (unsigned char **)&w.stg_c, (size_t)n * 4 * rs));
+  ok = ok && need(dalloc(c, &w.ik_t, (size_t)n));
+  ok = ok && need(dalloc(c, &w.ik_c, (size_t)n));
   ok = ok && need(dalloc(c, &w.runs, (size_t)5 * enuf::kMaxRuns));
-  ok = ok && need(dalloc(c, &w.off_c, (size_t)2 * g.ncells + 1));
   ok = ok && need(dalloc(c, &w.counts, 4));
   ok = ok && need(dalloc(c, &w.scal, 4));
-  ok = ok && need(dalloc(c, &w.qpart, (size_t)3 * enuf::nblk_prep(g)));
+  ok = ok && need(dalloc(c, &w.qpart, (size_t)4 * sp.nblk));
   ok = ok && need(dalloc(c, &w.kpart, (size_t)enuf::nblk_z(g, precision == ENUF_FP64)));
   ok = ok && need(dalloc(c, &w.rpart, (size_t)enuf::nblk_pair(g)));
   ok = ok && need(dalloc(c, (unsigned char **)&w.grid, G * rs));

@@ -21,8 +21,14 @@ constexpr int kTileBins = 2 * kClasses;  // sort bins per tile: charged classes,
 constexpr int kMaxRuns = 256;        // neighbour (tile, class-range) runs read by one spread tile
 constexpr int kPairBlock = 256;      // threads per cell in the pair kernel
 constexpr int kPairChunk = 512;      // neighbour particles staged in LDS at a time
-constexpr int kScanBlock = 256;      // threads per scan block
-constexpr int kScanChunk = 4 * kScanBlock;  // bins per scan block
+constexpr int kSortBlock = 256;      // threads per block of the sort passes
+constexpr int kSortPer = 2048;       // particles per counting block (before the cap)
+constexpr int kSortMaxBlocks = 1024; // cap on counting blocks
+constexpr int kSortBuckets = 256;    // target buckets per order
+constexpr int kSortFineLog = 12;     // at most 2^12 keys per bucket
+constexpr int kSortChunkMax = 2048;  // particles grouped in LDS at a time by the staging pass
+constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass
+constexpr int kSortFineRegs = 8;     // particles per thread held in registers by the fine pass
 constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)
 
 // Geometry and parameters, passed by value to kernels.
@@ -39,25 +45,43 @@ struct Geom {
   double alpha, rc, ke;
 };
 
+// Two-level counting sort layout: particles are counted in `nblk` blocks of
+// `per`; the keys of order o (0 tile, 1 cell) are cut into nb[o] buckets of
+// 2^sh[o] consecutive keys; the staging pass groups `chunk` particles at a
+// time in LDS (0: no grouping, for bucket counts too large for that).
+struct SortPlan {
+  int nblk;
+  int per;
+  int chunk;
+  int sh[2];
+  int nb[2];
+  int nbins[2];  // keys per order: kTileBins*ntiles, 2*ncells
+};
+SortPlan sort_plan(const Geom &g, int real_bytes);
+size_t sort_stage_lds(const SortPlan &sp, int real_bytes);
+size_t sort_fine_lds(const SortPlan &sp);
+
 // Device workspace pointers (all owned by the context).
 struct Work {
   void *part_t = nullptr;   // real4 [n] grid coords (s_x, s_y, s_z) + q, tile order
   void *part_c = nullptr;   // real4 [n] wrapped positions + q, cell order
   int *perm_t = nullptr;    // [n]
   int *perm_c = nullptr;    // [n]
-  int *key_t = nullptr;     // [n]
-  int *rank_t = nullptr;    // [n]
-  int *key_c = nullptr;     // [n]
-  int *rank_c = nullptr;    // [n]
-  int *off_t = nullptr;     // [kTileBins*ntiles + 1] counts, then exclusive offsets
-  int *off_c = nullptr;     // [2*ncells + 1]
-  int *bsum = nullptr;      // [scan blocks] block totals, then block prefixes
-  int *bev = nullptr;       // [scan blocks] charged subtotals
+  int *key_t = nullptr;     // [n] tile key per input particle; later the fine ranks (bucket order)
+  int *key_c = nullptr;     // [n] cell key per input particle; later the fine ranks
+  int *off_t = nullptr;     // [kTileBins*ntiles + 1] exclusive bin offsets, tile order
+  int *off_c = nullptr;     // [2*ncells + 1] exclusive bin offsets, cell order
+  int *hist = nullptr;      // [nblk][nb0 + nb1] per-block bucket counts, then block slots
+  int *bbase = nullptr;     // [nb0 + 1 + nb1 + 1] bucket starts of each order and totals
+  void *stg_t = nullptr;    // real4 [n] grid coords + q, bucket order (tile)
+  void *stg_c = nullptr;    // real4 [n] wrapped positions + q, bucket order (cell)
+  int2 *ik_t = nullptr;     // [n] (source index, key), bucket order
+  int2 *ik_c = nullptr;
   int *runs = nullptr;      // [5*nruns] spread neighbour runs (dx, dy, dz, class lo, class hi)
   int nruns = 0;
   int *counts = nullptr;    // [4]: active, charged, flags, spare
   double *scal = nullptr;   // [4]: Q, Q2, max abs(q), spare
-  double *qpart = nullptr;  // [3*nblk_prep] partial sums of q, q^2 and max abs(q)
+  double *qpart = nullptr;  // [4*nblk] per counting block: sum q, sum q^2, max abs(q), charged count
   double *kpart = nullptr;  // [nblk_z] partial reciprocal energies
   double *rpart = nullptr;  // [ncells] partial real-space energies
   void *grid = nullptr;     // real [G]
@@ -69,13 +93,13 @@ struct Work {
 };
 
 // Launch-configuration numbers the host needs to size partial buffers.
-int nblk_prep(const Geom &g);
 int nblk_pair(const Geom &g);
-int nblk_scan(const Geom &g);
 // Runs of (neighbour tile offset, class range) a spread tile reads; returns
 // the number of runs and writes 5 ints per run into out (kMaxRuns capacity).
 int build_runs(const Geom &g, int *out);
 int nblk_z(const Geom &g, bool fp64);
+// Every transform pass of the grid fits one workgroup's LDS.
+bool fft_plans_fit(const Geom &g, bool fp64);
 
 // Fill the twiddle / window tables on the host (size in reals returned by
 // table_size()).  `host` must hold table_size(g) reals of the precision.

@@ -1,8 +1,9 @@
 // enuf_kernels.hip -- HIP kernels of the ENUF hot path for gfx950 (CDNA4).
 //
 // One evaluation (paper Sec. 3.1-3.2) runs these phases on one stream:
-//   prep      wrap positions, bin keys, counting-sort ranks, charge sums
-//   sort      exclusive scan of the bins, scatter to tile / cell order
+//   prep      wrap positions, bin keys, per-block bucket counts, charge sums
+//   sort      bucket slots, staging into buckets, per-bucket counting sort
+//             into tile / cell order (no global atomics)
 //   spread    type-1 NFFT gridding step (Eq. 36): B-spline window, one
 //             workgroup per grid tile accumulating in LDS (no global atomics)
 //   fft_fwd   real-to-complex transform along x, complex along y (LDS pencils)
@@ -200,83 +201,8 @@ __global__ void k_fill_real(R *p, long long n) {
     p[i] = R(0);
 }
 
-// --------------------------------------------------------------------------
-// prep: wrap, keys, counting-sort ranks, charge sums
-//
-// Reciprocal-path key: (tile, charged/neutral, spill class).  Along each axis
-// a particle's stencil either stays inside its tile (digit 1), crosses the low
-// face (digit 0) or the high face (digit 2); the class is the three digits.
-// With that order a tile can read, from each neighbouring tile, exactly the
-// particles whose stencils reach it, as a few contiguous runs.
-// --------------------------------------------------------------------------
-__device__ __forceinline__ int spill_digit(int local, int T, int P) {
-  if (local < P / 2 - 1) return 0;
-  if (local > T - 1 - P / 2) return 2;
-  return 1;
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_prep(const R *__restrict__ x, const R *__restrict__ q, Geom g,
-                                                 int all_active, int *__restrict__ key_t,
-                                                 int *__restrict__ rank_t, int *__restrict__ key_c,
-                                                 int *__restrict__ rank_c, int *cnt_t, int *cnt_c,
-                                                 R *F, R *phi, double *qpart, int *counts) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double qs = 0.0, q2 = 0.0, qa = 0.0;
-  if (i < g.n) {
-    const R px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2], qi = q[i];
-    const bool fin = isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(qi);
-    if (!fin) atomicOr(&counts[2], 1);
-    const bool active = fin && (qi != R(0) || all_active);
-    if (fin) {
-      qs = (double)qi;
-      q2 = (double)qi * (double)qi;
-      qa = fabs((double)qi);
-    }
-    if (active) {
-      const R p3[3] = {px, py, pz};
-      int tix[3], cix[3], dig[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const R xw = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
-        const R sg = grid_coord(xw, R(g.M[d] / g.L[d]), g.M[d]);
-        const int gi = (int)sg;
-        tix[d] = gi / g.T[d];
-        dig[d] = spill_digit(gi - tix[d] * g.T[d], g.T[d], g.p);
-        const int ci = (int)(xw * R(g.nc[d] / g.L[d]));
-        cix[d] = ci < g.nc[d] ? ci : g.nc[d] - 1;
-      }
-      const int neutral = (qi == R(0)) ? 1 : 0;
-      const int tile = (tix[2] * g.nt[1] + tix[1]) * g.nt[0] + tix[0];
-      const int kt = tile * kTileBins + neutral * kClasses + (dig[0] * 9 + dig[1] * 3 + dig[2]);
-      const int kc = 2 * ((cix[2] * g.nc[1] + cix[1]) * g.nc[0] + cix[0]) + neutral;
-      key_t[i] = kt;
-      key_c[i] = kc;
-      rank_t[i] = atomicAdd(&cnt_t[kt], 1);
-      rank_c[i] = atomicAdd(&cnt_c[kc], 1);
-    } else {
-      key_t[i] = -1;
-      key_c[i] = -1;
-      if (F) { F[3 * i] = R(0); F[3 * i + 1] = R(0); F[3 * i + 2] = R(0); }
-      if (phi) phi[i] = R(0);
-    }
-  }
-  const double a = block_sum(qs);
-  const double b = block_sum(q2);
-  const double m = block_max(qa);
-  if (threadIdx.x == 0) {
-    qpart[3 * blockIdx.x] = a;
-    qpart[3 * blockIdx.x + 1] = b;
-    qpart[3 * blockIdx.x + 2] = m;
-  }
-}
-
-// Exclusive scans of the two bin arrays, in three launches:
-//  scan1: each block scans kScanChunk bins in place (within-block prefix) and
-//         writes its total (and, for the tile bins, its charged subtotal)
-//  scan2: one block scans the block totals of each array, writes the grand
-//         totals, the active/charged counts and the charge sums
-//  scan3: each block adds its block prefix to its bins
+// Exclusive scan of one int per thread over the block (blockDim.x a multiple
+// of 64, <= 1024); the block total goes to *total.
 __device__ int block_exscan_int(int v, int *total) {
   __shared__ int wsum[16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -299,127 +225,424 @@ __device__ int block_exscan_int(int v, int *total) {
   return before + inc - v;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan1(int *off_t, int nbt, int *off_c, int nbc, int bt,
-                                                      int *bsum, int *bev) {
-  const int b = blockIdx.x;
-  const bool tiles = b < bt;
-  int *arr = tiles ? off_t : off_c;
-  const int len = tiles ? nbt : nbc;
-  const int base = (tiles ? b : b - bt) * kScanChunk;
-  const int i0 = base + threadIdx.x * 4;
-  int v[4], s = 0, ev = 0;
+// --------------------------------------------------------------------------
+// prep and sort: wrap, bin keys, two-level counting sort, charge sums
+//
+// Reciprocal-path key: (tile, charged/neutral, spill class).  Along each axis
+// a particle's stencil either stays inside its tile (digit 1), crosses the low
+// face (digit 0) or the high face (digit 2); the class is the three digits.
+// With that order a tile can read, from each neighbouring tile, exactly the
+// particles whose stencils reach it, as a few contiguous runs.
+// Real-space key: (cell, charged/neutral).
+//
+// Both orders are built without global atomics.  Each key range is cut into
+// buckets of 2^sh consecutive keys.  Pass 1 counts, per block of particles,
+// the particles of each bucket in LDS; a column scan and a bucket scan turn the
+// per-block counts into each block's first slot in every bucket; pass 2 moves
+// every particle to its bucket (slots taken with LDS atomics); pass 3 sorts
+// one bucket per workgroup by its fine key in LDS and writes the final order
+// and the bin offsets.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int spill_digit(int local, int T, int P) {
+  if (local < P / 2 - 1) return 0;
+  if (local > T - 1 - P / 2) return 2;
+  return 1;
+}
+
+// Wrapped position and grid coordinate of one particle (shared by the key
+// pass and the staging pass, so both see the same values).
+template <typename R>
+__device__ __forceinline__ void particle_coords(const R (&p3)[3], const Geom &g, R (&xw)[3], R (&sg)[3]) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = (i0 + k < len) ? arr[i0 + k] : 0;
-    s += v[k];
-    if (tiles && ((i0 + k) % kTileBins) < kClasses) ev += v[k];
-  }
-  int tot;
-  int run = block_exscan_int(s, &tot);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (i0 + k < len) arr[i0 + k] = run;
-    run += v[k];
-  }
-  int evt;
-  (void)block_exscan_int(ev, &evt);
-  if (threadIdx.x == 0) {
-    bsum[b] = tot;
-    bev[b] = evt;
+  for (int d = 0; d < 3; ++d) {
+    xw[d] = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
+    sg[d] = grid_coord(xw[d], R(g.M[d] / g.L[d]), g.M[d]);
   }
 }
 
-__global__ __launch_bounds__(1024) void k_scan2(int *bsum, const int *bev, int bt, int bc, int *off_t, int nbt,
-                                                int *off_c, int nbc, const double *qpart, int nqp, double *scal,
-                                                int *counts) {
+template <typename R>
+__device__ __forceinline__ void particle_keys(const R (&xw)[3], const R (&sg)[3], bool neutral, const Geom &g,
+                                              int &kt, int &kc) {
+  int tix[3], cix[3], dig[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int gi = (int)sg[d];
+    tix[d] = gi / g.T[d];
+    dig[d] = spill_digit(gi - tix[d] * g.T[d], g.T[d], g.p);
+    const int ci = (int)(xw[d] * R(g.nc[d] / g.L[d]));
+    cix[d] = ci < g.nc[d] ? ci : g.nc[d] - 1;
+  }
+  const int nt = neutral ? 1 : 0;
+  const int tile = (tix[2] * g.nt[1] + tix[1]) * g.nt[0] + tix[0];
+  kt = tile * kTileBins + nt * kClasses + (dig[0] * 9 + dig[1] * 3 + dig[2]);
+  kc = 2 * ((cix[2] * g.nc[1] + cix[1]) * g.nc[0] + cix[0]) + nt;
+}
+
+// Pass 1: keys of every particle (-1 for inactive ones, whose outputs are
+// zeroed here), per-block bucket counts hist[blk][bucket] (tile buckets, then
+// cell buckets), per-block sums of q, q^2, max |q| and the charged count.
+template <typename R>
+__global__ __launch_bounds__(kSortBlock) void k_sort_count(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+                                                           SortPlan sp, int all_active, int *__restrict__ key_t,
+                                                           int *__restrict__ key_c, int *__restrict__ hist,
+                                                           R *F, R *phi, double *qpart, int *counts) {
+  extern __shared__ int cnt[];
+  const int nbk = sp.nb[0] + sp.nb[1];
+  for (int b = threadIdx.x; b < nbk; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  const long long i0 = (long long)blockIdx.x * sp.per;
+  const int i1 = (int)min((long long)g.n, i0 + sp.per);
+  double qs = 0.0, q2 = 0.0, qa = 0.0, nq = 0.0;
+  for (int i = (int)i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+    const R qi = q[i];
+    const bool fin = isfinite(p3[0]) && isfinite(p3[1]) && isfinite(p3[2]) && isfinite(qi);
+    if (!fin) atomicOr(&counts[2], 1);
+    const bool active = fin && (qi != R(0) || all_active);
+    if (fin) {
+      qs += (double)qi;
+      q2 += (double)qi * (double)qi;
+      qa = fmax(qa, fabs((double)qi));
+    }
+    if (active) {
+      R xw[3], sg[3];
+      particle_coords(p3, g, xw, sg);
+      int kt, kc;
+      particle_keys(xw, sg, qi == R(0), g, kt, kc);
+      key_t[i] = kt;
+      key_c[i] = kc;
+      atomicAdd(&cnt[kt >> sp.sh[0]], 1);
+      atomicAdd(&cnt[sp.nb[0] + (kc >> sp.sh[1])], 1);
+      if (qi != R(0)) nq += 1.0;
+    } else {
+      key_t[i] = -1;
+      key_c[i] = -1;
+      if (F) { F[3 * i] = R(0); F[3 * i + 1] = R(0); F[3 * i + 2] = R(0); }
+      if (phi) phi[i] = R(0);
+    }
+  }
+  __syncthreads();
+  int *row = hist + (size_t)blockIdx.x * nbk;
+  for (int b = threadIdx.x; b < nbk; b += blockDim.x) row[b] = cnt[b];
+  const double a = block_sum(qs);
+  const double b2 = block_sum(q2);
+  const double m = block_max(qa);
+  const double c = block_sum(nq);
+  if (threadIdx.x == 0) {
+    qpart[4 * blockIdx.x] = a;
+    qpart[4 * blockIdx.x + 1] = b2;
+    qpart[4 * blockIdx.x + 2] = m;
+    qpart[4 * blockIdx.x + 3] = c;
+  }
+}
+
+// Exclusive scan over the blocks of each bucket column of hist (in place);
+// the column total goes to the bucket's slot of bbase.  64 columns per
+// workgroup, 16 row groups of 64 lanes each.
+__device__ __forceinline__ int bucket_slot(const SortPlan &sp, int b) { return b < sp.nb[0] ? b : b + 1; }
+
+__global__ __launch_bounds__(1024) void k_sort_colscan(int *__restrict__ hist, SortPlan sp, int *__restrict__ bbase) {
+  __shared__ int part[16][64];
+  const int nbk = sp.nb[0] + sp.nb[1];
+  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  const int rows = (sp.nblk + 15) / 16;
+  const int r0 = rg * rows, r1 = min(sp.nblk, r0 + rows);
+  int s = 0;
+  if (col < nbk) {
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += hist[(size_t)r * nbk + col];
+  }
+  part[rg][lane] = s;
+  __syncthreads();
+  int run = 0;
+  for (int k = 0; k < rg; ++k) run += part[k][lane];
+  if (col < nbk) {
+    if (rg == 15) bbase[bucket_slot(sp, col)] = run + s;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) {
+      int *h = hist + (size_t)r * nbk + col;
+      const int v = *h;
+      *h = run;
+      run += v;
+    }
+  }
+}
+
+// Exclusive scan of the bucket totals of each order (in place in bbase, the
+// grand total after the last bucket), the bin-offset terminators, the active
+// and charged counts and the charge sums.
+__global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, SortPlan sp, int *off_t, int *off_c,
+                                                    const double *__restrict__ qpart, double *scal, int *counts) {
   __shared__ int carry;
   for (int seg = 0; seg < 2; ++seg) {
-    const int lo = seg == 0 ? 0 : bt, n = seg == 0 ? bt : bc;
+    const int lo = seg == 0 ? 0 : sp.nb[0] + 1, n = sp.nb[seg];
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += blockDim.x) {
       const int i = c0 + threadIdx.x;
-      const int v = i < n ? bsum[lo + i] : 0;
+      const int v = i < n ? bbase[lo + i] : 0;
       int tot;
       const int ex = block_exscan_int(v, &tot);
       const int cy = carry;
-      if (i < n) bsum[lo + i] = cy + ex;
+      if (i < n) bbase[lo + i] = cy + ex;
       __syncthreads();
       if (threadIdx.x == 0) carry = cy + tot;
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      if (seg == 0) { off_t[nbt] = carry; counts[0] = carry; }
-      else off_c[nbc] = carry;
+      bbase[lo + n] = carry;
+      if (seg == 0) { off_t[sp.nbins[0]] = carry; counts[0] = carry; }
+      else off_c[sp.nbins[1]] = carry;
     }
     __syncthreads();
   }
-  int ev = 0;
-  for (int i = threadIdx.x; i < bt; i += blockDim.x) ev += bev[i];
-  double a = 0.0, b = 0.0, m = 0.0;
-  for (int i = threadIdx.x; i < nqp; i += blockDim.x) {
-    a += qpart[3 * i];
-    b += qpart[3 * i + 1];
-    m = fmax(m, qpart[3 * i + 2]);
+  double a = 0.0, b = 0.0, m = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < sp.nblk; i += blockDim.x) {
+    a += qpart[4 * i];
+    b += qpart[4 * i + 1];
+    m = fmax(m, qpart[4 * i + 2]);
+    c += qpart[4 * i + 3];
   }
-  const double evd = block_sum((double)ev);
   a = block_sum(a);
   b = block_sum(b);
   m = block_max(m);
+  c = block_sum(c);
   if (threadIdx.x == 0) {
-    counts[1] = (int)evd;
+    counts[1] = (int)c;
     scal[0] = a;
     scal[1] = b;
     scal[2] = m;
   }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan3(int *off_t, int nbt, int *off_c, int nbc, int bt,
-                                                      const int *bsum) {
-  const int b = blockIdx.x;
-  const bool tiles = b < bt;
-  int *arr = tiles ? off_t : off_c;
-  const int len = tiles ? nbt : nbc;
-  const int base = (tiles ? b : b - bt) * kScanChunk;
-  const int add = bsum[b];
-  for (int k = threadIdx.x; k < kScanChunk; k += blockDim.x)
-    if (base + k < len) arr[base + k] += add;
+// Pass 2: each active particle to the next free slot of its bucket, one order
+// after the other, in chunks of sp.chunk particles: the chunk is grouped by
+// bucket in LDS first, so each bucket's particles leave as one contiguous run.
+// Staged records: (s_x, s_y, s_z, q) for the tile order, (x_w, y_w, z_w, q)
+// for the cell order, each with (source index, key).
+template <typename R>
+__global__ __launch_bounds__(kSortBlock) void k_sort_stage(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+                                                           SortPlan sp, const int *__restrict__ key_t,
+                                                           const int *__restrict__ key_c,
+                                                           const int *__restrict__ hist,
+                                                           const int *__restrict__ bbase, real4<R> *stg_t,
+                                                           int2 *ik_t, real4<R> *stg_c, int2 *ik_c) {
+  constexpr int U = kSortChunkMax / kSortBlock;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int nbk = sp.nb[0] + sp.nb[1];
+  const int nbm = max(sp.nb[0], sp.nb[1]);
+  real4<R> *rec = reinterpret_cast<real4<R> *>(lds_raw);  // [chunk]
+  int2 *rik = reinterpret_cast<int2 *>(rec + sp.chunk);    // [chunk]
+  int *slot = reinterpret_cast<int *>(rik + sp.chunk);     // [nbm] the block's next free slot per bucket
+  int *cnt = slot + nbm;                                   // [nbm] chunk counts, then chunk starts
+  const int tid = threadIdx.x;
+  const int *row = hist + (size_t)blockIdx.x * nbk;
+  const long long i0 = (long long)blockIdx.x * sp.per;
+  const int i1 = (int)min((long long)g.n, i0 + sp.per);
+  for (int o = 0; o < 2; ++o) {
+    const int nb = sp.nb[o], sh = sp.sh[o];
+    const int *key = o == 0 ? key_t : key_c;
+    real4<R> *stg = o == 0 ? stg_t : stg_c;
+    int2 *ik = o == 0 ? ik_t : ik_c;
+    const int cb = o == 0 ? 0 : sp.nb[0];
+    const int sb = o == 0 ? 0 : sp.nb[0] + 1;
+    for (int b = tid; b < nb; b += blockDim.x) slot[b] = bbase[sb + b] + row[cb + b];
+    if (sp.chunk == 0) {
+      // ungrouped: every particle straight to its slot
+      __syncthreads();
+      for (int i = (int)i0 + tid; i < i1; i += blockDim.x) {
+        const int k = key[i];
+        if (k < 0) continue;
+        const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        R xw[3], sg[3];
+        particle_coords(p3, g, xw, sg);
+        real4<R> a;
+        a.x = o == 0 ? sg[0] : xw[0];
+        a.y = o == 0 ? sg[1] : xw[1];
+        a.z = o == 0 ? sg[2] : xw[2];
+        a.w = q[i];
+        const int p = atomicAdd(&slot[k >> sh], 1);
+        stg[p] = a;
+        ik[p] = make_int2(i, k);
+      }
+      __syncthreads();
+      continue;
+    }
+    for (int c0 = (int)i0; c0 < i1; c0 += sp.chunk) {
+      for (int b = tid; b < nb; b += blockDim.x) cnt[b] = 0;
+      __syncthreads();
+      int kk[U], rr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = c0 + u * kSortBlock + tid;
+        kk[u] = (u * kSortBlock < sp.chunk && i < i1) ? key[i] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) rr[u] = kk[u] >= 0 ? atomicAdd(&cnt[kk[u] >> sh], 1) : 0;
+      __syncthreads();
+      // chunk starts per bucket: exclusive scan, each thread a run of buckets
+      const int per = (nb + blockDim.x - 1) / blockDim.x;
+      const int b0 = tid * per, b1 = min(nb, b0 + per);
+      int sum = 0;
+      for (int b = b0; b < b1; ++b) sum += cnt[b];
+      int m;
+      int run = block_exscan_int(sum, &m);
+      for (int b = b0; b < b1; ++b) {
+        const int v = cnt[b];
+        cnt[b] = run;
+        run += v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (kk[u] < 0) continue;
+        const int i = c0 + u * kSortBlock + tid;
+        const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        R xw[3], sg[3];
+        particle_coords(p3, g, xw, sg);
+        real4<R> a;
+        a.x = o == 0 ? sg[0] : xw[0];
+        a.y = o == 0 ? sg[1] : xw[1];
+        a.z = o == 0 ? sg[2] : xw[2];
+        a.w = q[i];
+        const int p = cnt[kk[u] >> sh] + rr[u];
+        rec[p] = a;
+        rik[p] = make_int2(i, kk[u]);
+      }
+      __syncthreads();
+      for (int t = tid; t < m; t += blockDim.x) {
+        const int2 v = rik[t];
+        const int b = v.y >> sh;
+        const int pos = slot[b] + (t - cnt[b]);
+        stg[pos] = rec[t];
+        ik[pos] = v;
+      }
+      __syncthreads();
+      // advance the slots by the chunk's counts
+      for (int b = tid; b < nb; b += blockDim.x) slot[b] += (b + 1 < nb ? cnt[b + 1] : m) - cnt[b];
+      __syncthreads();
+    }
+  }
 }
 
+// Pass 3: one workgroup per bucket (tile buckets, then cell buckets): counting
+// sort of the bucket's particles by fine key in LDS, bin offsets of the
+// bucket's keys, particles and source indices in final order.  A bucket of at
+// most kSortFineRegs*blockDim particles keeps keys and ranks in registers and
+// builds the inverse permutation in LDS, so the final order is written
+// contiguously (reads gathered from the staged bucket instead); a larger one
+// goes through global ranks and scattered writes.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_scatter(const R *__restrict__ x, const R *__restrict__ q, Geom g,
-                                                    const int *__restrict__ key_t, const int *__restrict__ rank_t,
-                                                    const int *__restrict__ key_c, const int *__restrict__ rank_c,
-                                                    const int *__restrict__ off_t, const int *__restrict__ off_c,
-                                                    real4<R> *part_t, int *perm_t, real4<R> *part_c, int *perm_c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
-  const int kt = key_t[i];
-  if (kt < 0) return;
-  const R px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2], qi = q[i];
-  const R p3[3] = {px, py, pz};
-  R xw[3], sg[3];
+__global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const int *__restrict__ bbase,
+                                                              const real4<R> *__restrict__ stg_t,
+                                                              const int2 *__restrict__ ik_t, int *srank_t,
+                                                              const real4<R> *__restrict__ stg_c,
+                                                              const int2 *__restrict__ ik_c, int *srank_c,
+                                                              real4<R> *part_t, int *perm_t, int *off_t,
+                                                              real4<R> *part_c, int *perm_c, int *off_c) {
+  constexpr int U = kSortFineRegs;
+  extern __shared__ int lds_fine[];
+  const bool tiles = (int)blockIdx.x < sp.nb[0];
+  const int b = tiles ? blockIdx.x : blockIdx.x - sp.nb[0];
+  const int o = tiles ? 0 : 1;
+  const int slot = tiles ? b : sp.nb[0] + 1 + b;
+  const int s = bbase[slot], e = bbase[slot + 1];
+  const int k0 = b << sp.sh[o];
+  const int nf = min(1 << sp.sh[o], sp.nbins[o] - k0);
+  const real4<R> *stg = tiles ? stg_t : stg_c;
+  const int2 *ik = tiles ? ik_t : ik_c;
+  int *srank = tiles ? srank_t : srank_c;
+  real4<R> *part = tiles ? part_t : part_c;
+  int *perm = tiles ? perm_t : perm_c;
+  int *off = tiles ? off_t : off_c;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  int *bin = lds_fine;                                   // [2^max sh] counts, then starts
+  int *inv = lds_fine + (1 << max(sp.sh[0], sp.sh[1]));  // [U*nt] bucket position -> staged index
+  const bool small = e - s <= U * nt;
+
+  for (int f = tid; f < nf; f += nt) bin[f] = 0;
+  __syncthreads();
+  int kk[U], rr[U];
+  if (small) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    xw[d] = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
-    sg[d] = grid_coord(xw[d], R(g.M[d] / g.L[d]), g.M[d]);
+    for (int u = 0; u < U; ++u) {
+      const int j = s + u * nt + tid;
+      kk[u] = j < e ? ik[j].y - k0 : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) rr[u] = (unsigned)kk[u] < (unsigned)nf ? atomicAdd(&bin[kk[u]], 1) : 0;
+  } else {
+    for (int j0 = s + tid; j0 < e; j0 += U * nt) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * nt;
+        kk[u] = j < e ? ik[j].y - k0 : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * nt;
+        if (j < e) srank[j] = (unsigned)kk[u] < (unsigned)nf ? atomicAdd(&bin[kk[u]], 1) : 0;
+      }
+    }
   }
-  const int pt = off_t[kt] + rank_t[i];
-  real4<R> a;
-  a.x = sg[0];
-  a.y = sg[1];
-  a.z = sg[2];
-  a.w = qi;
-  part_t[pt] = a;
-  perm_t[pt] = i;
-  const int pc = off_c[key_c[i]] + rank_c[i];
-  real4<R> b;
-  b.x = xw[0];
-  b.y = xw[1];
-  b.z = xw[2];
-  b.w = qi;
-  part_c[pc] = b;
-  perm_c[pc] = i;
+  __syncthreads();
+  // exclusive scan of the nf counts: each thread owns a run of consecutive bins
+  const int per = (nf + nt - 1) / nt;
+  const int f0 = tid * per, f1 = min(nf, f0 + per);
+  int sum = 0;
+  for (int f = f0; f < f1; ++f) sum += bin[f];
+  int tot;
+  int run = block_exscan_int(sum, &tot);
+  for (int f = f0; f < f1; ++f) {
+    const int v = bin[f];
+    bin[f] = run;
+    off[k0 + f] = s + run;
+    run += v;
+  }
+  __syncthreads();
+  if (small) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if ((unsigned)kk[u] < (unsigned)nf) inv[bin[kk[u]] + rr[u]] = u * nt + tid;
+    __syncthreads();
+    for (int t0 = tid; t0 < e - s; t0 += 4 * nt) {
+      int jj[4];
+      pod_t<real4<R>> a[4];
+      int pv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int v = t0 + u * nt < e - s ? inv[t0 + u * nt] : -1;
+        jj[u] = (unsigned)v < (unsigned)(e - s) ? s + v : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (jj[u] >= 0) {
+          a[u] = *reinterpret_cast<const pod_t<real4<R>> *>(stg + jj[u]);
+          pv[u] = ik[jj[u]].x;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (jj[u] >= 0) {
+          *reinterpret_cast<pod_t<real4<R>> *>(part + s + t0 + u * nt) = a[u];
+          perm[s + t0 + u * nt] = pv[u];
+        }
+    }
+  } else {
+    for (int j0 = s + tid; j0 < e; j0 += U * nt) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * nt;
+        if (j >= e) continue;
+        const int2 v = ik[j];
+        const int k = v.y - k0;
+        if ((unsigned)k >= (unsigned)nf) continue;
+        const int pos = s + bin[k] + srank[j];
+        part[pos] = stg[j];
+        perm[pos] = v.x;
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1735,11 +1958,37 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *kpart, int nk, 
 // --------------------------------------------------------------------------
 // host side: tables and launch sequences
 // --------------------------------------------------------------------------
-int nblk_prep(const Geom &g) { return (g.n + kBlock - 1) / kBlock; }
 int nblk_pair(const Geom &g) { return g.ncells; }
-static int scan_bt(const Geom &g) { return (kTileBins * g.ntiles + kScanChunk - 1) / kScanChunk; }
-static int scan_bc(const Geom &g) { return (2 * g.ncells + kScanChunk - 1) / kScanChunk; }
-int nblk_scan(const Geom &g) { return scan_bt(g) + scan_bc(g); }
+
+size_t sort_stage_lds(const SortPlan &sp, int real_bytes) {
+  const size_t nbm = std::max(sp.nb[0], sp.nb[1]);
+  if (sp.chunk == 0) return nbm * sizeof(int);
+  return (size_t)sp.chunk * (4 * real_bytes + 8) + 2 * nbm * sizeof(int);
+}
+
+size_t sort_fine_lds(const SortPlan &sp) {
+  return ((size_t)(1 << std::max(sp.sh[0], sp.sh[1])) + (size_t)kSortFineRegs * kSortFineBlock) * sizeof(int);
+}
+
+SortPlan sort_plan(const Geom &g, int real_bytes) {
+  SortPlan sp{};
+  sp.nblk = std::max(1, std::min(kSortMaxBlocks, (g.n + kSortPer - 1) / kSortPer));
+  sp.per = (g.n + sp.nblk - 1) / sp.nblk;
+  sp.nbins[0] = kTileBins * g.ntiles;
+  sp.nbins[1] = 2 * g.ncells;
+  for (int o = 0; o < 2; ++o) {
+    int sh = 0;
+    while (sh < kSortFineLog && ((sp.nbins[o] + (1 << sh) - 1) >> sh) > kSortBuckets) ++sh;
+    sp.sh[o] = sh;
+    sp.nb[o] = (sp.nbins[o] + (1 << sh) - 1) >> sh;
+  }
+  // largest staging chunk (a multiple of the block) that fits 64 KB of LDS;
+  // zero (ungrouped staging) if none does
+  for (sp.chunk = kSortChunkMax; sp.chunk >= kSortBlock; sp.chunk /= 2)
+    if (sort_stage_lds(sp, real_bytes) <= 65536) break;
+  if (sp.chunk < kSortBlock) sp.chunk = 0;
+  return sp;
+}
 
 int build_runs(const Geom &g, int *out) {
   int n = 0;
@@ -1847,6 +2096,15 @@ static FftPlan fft_plan(const Geom &g, size_t cs, int nf) {
   P.lb_c2r = pick(g.M[1] * g.M[2], c2r, 32768);
   P.lds_c2r = c2r(P.lb_c2r);
   return P;
+}
+
+bool fft_plans_fit(const Geom &g, bool fp64) {
+  const size_t cs = fp64 ? 16 : 8;
+  for (int nf : {1, 3, 4}) {
+    const FftPlan P = fft_plan(g, cs, nf);
+    if (P.lds_r2c > 65536 || P.lds_y > 65536 || P.lds_z > 65536 - 512 || P.lds_c2r > 65536) return false;
+  }
+  return true;
 }
 
 int nblk_z(const Geom &g, bool fp64) {
@@ -1993,27 +2251,27 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
 
   mark(0);
-  // prep
-  const int nbt = kTileBins * g.ntiles, nbc = 2 * g.ncells;
-  hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(kBlock), 0, st, w.off_t, nbt + 1, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(kBlock), 0, st, w.off_c, nbc + 1, 0);
-  hipLaunchKernelGGL((k_prep<R>), dim3(nblk_prep(g)), dim3(kBlock), 0, st, x, q, g, all_active ? 1 : 0,
-                     w.key_t, w.rank_t, w.key_c, w.rank_c, w.off_t, w.off_c, F, phi, w.qpart, w.counts);
+  // prep: keys and per-block bucket counts
+  const SortPlan sp = sort_plan(g, (int)sizeof(R));
+  const int nbk = sp.nb[0] + sp.nb[1];
+  const size_t lds_cnt = (size_t)nbk * sizeof(int);
+  const size_t lds_fine = sort_fine_lds(sp);
+  hipLaunchKernelGGL((k_sort_count<R>), dim3(sp.nblk), dim3(kSortBlock), lds_cnt, st, x, q, g, sp,
+                     all_active ? 1 : 0, w.key_t, w.key_c, w.hist, F, phi, w.qpart, w.counts);
   ENUF_TRY(hipGetLastError());
   mark(1);
-  // sort
-  {
-    const int bt = scan_bt(g), bc = scan_bc(g);
-    hipLaunchKernelGGL(k_scan1, dim3(bt + bc), dim3(kScanBlock), 0, st, w.off_t, nbt, w.off_c, nbc, bt, w.bsum,
-                       w.bev);
-    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(1024), 0, st, w.bsum, (const int *)w.bev, bt, bc, w.off_t, nbt,
-                       w.off_c, nbc, (const double *)w.qpart, nblk_prep(g), w.scal, w.counts);
-    hipLaunchKernelGGL(k_scan3, dim3(bt + bc), dim3(kScanBlock), 0, st, w.off_t, nbt, w.off_c, nbc, bt,
-                       (const int *)w.bsum);
-  }
-  hipLaunchKernelGGL((k_scatter<R>), dim3(nblk_prep(g)), dim3(kBlock), 0, st, x, q, g, w.key_t, w.rank_t,
-                     w.key_c, w.rank_c, w.off_t, w.off_c, (real4<R> *)w.part_t, w.perm_t,
-                     (real4<R> *)w.part_c, w.perm_c);
+  // sort: slots, bucket staging, fine sort per bucket (the key arrays are
+  // dead after staging and take the fine ranks)
+  hipLaunchKernelGGL(k_sort_colscan, dim3((nbk + 63) / 64), dim3(1024), 0, st, w.hist, sp, w.bbase);
+  hipLaunchKernelGGL(k_sort_base, dim3(1), dim3(1024), 0, st, w.bbase, sp, w.off_t, w.off_c,
+                     (const double *)w.qpart, w.scal, w.counts);
+  hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
+                     x, q, g, sp, (const int *)w.key_t, (const int *)w.key_c, (const int *)w.hist,
+                     (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c);
+  hipLaunchKernelGGL((k_sort_fine<R>), dim3(nbk), dim3(kSortFineBlock), lds_fine, st, sp, (const int *)w.bbase,
+                     (const real4<R> *)w.stg_t, (const int2 *)w.ik_t, w.key_t, (const real4<R> *)w.stg_c,
+                     (const int2 *)w.ik_c, w.key_c, (real4<R> *)w.part_t, w.perm_t, w.off_t,
+                     (real4<R> *)w.part_c, w.perm_c, w.off_c);
   ENUF_TRY(hipGetLastError());
   mark(2);
   // spread

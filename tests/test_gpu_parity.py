@@ -252,6 +252,17 @@ def test_window_orders_and_small_grids(p, M):
     _compare(out, m, "f64")
 
 
+@pytest.mark.parametrize("M", [(1024, 16, 16), (16, 1024, 16), (16, 16, 1024), (512, 16, 256)])
+def test_longest_axes_vs_mirror(M):
+    # the largest transform lengths (1024 points: three radix stages, the
+    # widest LDS pencils; the x pass of 1024 reals is a 512-point transform)
+    box = tuple(0.04 * m + 7.0 for m in M)
+    x, q, box = _random_system(600, box, seed=sum(M))
+    eng, out = run(x, q, box, 1.2, 3.4, M, 6)
+    m = em.enuf(x, q, box, 1.2, 3.4, M, 6, want_grad=False)
+    _compare(out, m, "f64")
+
+
 def test_positions_on_box_faces_and_far_outside():
     L = 6.0
     box = np.array([L, L, L])
