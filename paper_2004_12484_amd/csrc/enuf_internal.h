@@ -20,7 +20,6 @@ constexpr int kClasses = 27;         // stencil spill classes per tile (3 digits
 constexpr int kTileBins = 2 * kClasses;  // sort bins per tile: charged classes, then neutral
 constexpr int kMaxRuns = 256;        // neighbour (tile, class-range) runs read by one spread tile
 constexpr int kPairBlock = 256;      // threads per cell in the pair kernel
-constexpr int kPairChunk = 512;      // neighbour particles staged in LDS at a time
 constexpr int kSortBlock = 256;      // threads per block of the sort passes
 constexpr int kSortPer = 2048;       // particles per counting block (before the cap)
 constexpr int kSortMaxBlocks = 1024; // cap on counting blocks

@@ -1728,6 +1728,10 @@ __device__ __forceinline__ unsigned long long cut_limit(double rc2) {
   return (unsigned long long)__double_as_longlong(rc2) - 1ull;
 }
 
+// candidates staged per chunk: 12 KB of LDS in either precision
+template <typename R>
+constexpr int pair_chunk() { return sizeof(R) == 4 ? 768 : 384; }
+
 template <typename R, int MODE, bool MINIMG>
 __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict__ part,
                                                      const int *__restrict__ perm,
@@ -1735,7 +1739,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
                                                      const double *__restrict__ scal, R gscale,
                                                      R *__restrict__ out_vec, R *__restrict__ out_sca,
                                                      double *rpart) {
-  __shared__ real4<R> cand[kPairChunk];
+  constexpr int CH = pair_chunk<R>();
+  __shared__ real4<R> cand[CH];
   __shared__ R red[kPairBlock][4];
   __shared__ int rs[27], rp[28];
   __shared__ R rsh[27][3];  // periodic image shift of each neighbour cell
@@ -1836,44 +1841,65 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
       if (mi2) ddz -= L2 * rint(ddz * iL2);
       return u.w;
     };
-    for (int c0 = 0; c0 < ncand; c0 += kPairChunk) {
-      const int nc = min(kPairChunk, ncand - c0);
+    for (int c0 = 0; c0 < ncand; c0 += CH) {
+      const int nc = min(CH, ncand - c0);
       __syncthreads();
-      // stage candidates c0 .. c0+nc-1: every thread finds the range of its
-      // candidates by binary search, so all global loads are in flight at once
-      for (int k = tid; k < nc; k += blockDim.x) {
-        const int c = c0 + k;
-        int lo = 0, hi2 = 27;
-        while (hi2 - lo > 1) {
-          const int mid = (lo + hi2) >> 1;
-          if (rp[mid] <= c) lo = mid; else hi2 = mid;
+      {
+        // stage candidates c0 .. c0+nc-1: a team of 9 threads per neighbour
+        // cell copies that cell's part of the window, 9 consecutive particles
+        // per step (27 teams of 9 in a block of 256)
+        const int r = tid / 9, j0 = tid - 9 * (tid / 9);
+        if (r < 27) {
+          const int a0 = max(0, c0 - rp[r]), a1 = min(rp[r + 1] - rp[r], c0 + nc - rp[r]);
+          const R sx = rsh[r][0], sy = rsh[r][1], sz = rsh[r][2];
+          for (int k = a0 + j0; k < a1; k += 9) {
+            const pod_t<real4<R>> v = *reinterpret_cast<const pod_t<real4<R>> *>(part + rs[r] + k);
+            real4<R> u;
+            u.x = v[0] + sx;
+            u.y = v[1] + sy;
+            u.z = v[2] + sz;
+            u.w = v[3];
+            cand[rp[r] + k - c0] = u;
+          }
         }
-        real4<R> u = part[rs[lo] + (c - rp[lo])];
-        u.x += rsh[lo][0];
-        u.y += rsh[lo][1];
-        u.z += rsh[lo][2];
-        cand[k] = u;
       }
       __syncthreads();
       {
-        // pass 1 marks the candidates inside the cutoff in a 32-bit mask;
-        // pass 2 does the erfc/exp work for the marked ones only, so lanes
-        // that miss do not idle through it
+        // lane group grp takes candidates grp, grp + Gh, ... of the chunk (an
+        // interleaved share, so every lane sees a mix of near and far cells
+        // and the pass-2 work stays balanced), in rounds of up to 64.  Pass 1
+        // marks the candidates inside the cutoff in a 64-bit mask, four per
+        // unrolled step; pass 2 does the erfc/exp work for the marked ones
+        // only, so lanes that miss do not idle through it
         const auto lim = cut_limit(rc2);
-        const int nmine = (nc - grp + Gh - 1) / Gh;  // candidates grp, grp+Gh, ...
-        for (int m0 = 0; m0 < nmine; m0 += 32) {
-          unsigned mask = 0u;
-          const int mend = min(32, nmine - m0);
-          for (int b = 0; b < mend; ++b) {
+        const int nmine = (nc - grp + Gh - 1) / Gh;
+        for (int m0 = 0; m0 < nmine; m0 += 64) {
+          const int n64 = min(64, nmine - m0);
+          const int b0 = grp + Gh * m0;
+          unsigned long long mask = 0ull;
+          int k = 0;
+#pragma unroll 1
+          for (; k + 4 <= n64; k += 4) {
+            unsigned nib = 0u;
+            const int a = b0 + Gh * k;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              R ddx, ddy, ddz;
+              sep(a + Gh * b, ddx, ddy, ddz);
+              nib |= in_cut(ddx * ddx + ddy * ddy + ddz * ddz, lim) ? (1u << b) : 0u;
+            }
+            mask |= (unsigned long long)nib << k;
+          }
+          for (; k < n64; ++k) {
             R ddx, ddy, ddz;
-            sep(grp + Gh * (m0 + b), ddx, ddy, ddz);
-            if (in_cut(ddx * ddx + ddy * ddy + ddz * ddz, lim)) mask |= 1u << b;
+            sep(b0 + Gh * k, ddx, ddy, ddz);
+            if (in_cut(ddx * ddx + ddy * ddy + ddz * ddz, lim)) mask |= 1ull << k;
           }
           while (mask) {
-            const int b = __builtin_ctz(mask);
-            mask &= mask - 1u;
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1ull;
             R ddx, ddy, ddz;
-            const R qj = sep(grp + Gh * (m0 + b), ddx, ddy, ddz);
+            const R qj = sep(b0 + Gh * b, ddx, ddy, ddz);
             const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             const R ir = rsqrt_r(r2);
             const R r = r2 * ir;
