@@ -1507,10 +1507,9 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
   }
 }
 
-// Tile form of the gather: one workgroup per grid tile stages the tile's
-// fields plus the (P-1)-point halo in LDS, one 32-lane group per contiguous
-// x row (E0 <= 32 points), then interpolates every active particle of the
-// tile from LDS.  Four lanes share a particle: each sums the (z, y) rows of
+// Tile form of the gather: one workgroup per SY x SZ spread tiles stages
+// their fields plus the (P-1)-point halo in LDS, then interpolates every
+// active particle of those tiles from LDS.  Four lanes share a particle: each sums the (z, y) rows of
 // one parity pair (z even/odd x y even/odd; P is even) and the four partial
 // sums are combined with lane shuffles, so a tile of 64 particles keeps all
 // 256 lanes busy.  Used when
@@ -1529,7 +1528,7 @@ __device__ __forceinline__ double pick(int b, double x, double y) {
                                           ((unsigned long long)__double_as_longlong(y) & m)));
 }
 
-template <typename R, int P, bool GRAD, typename FT>
+template <typename R, int P, bool GRAD, typename FT, int SY, int SZ>
 __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
                                                                   const int *__restrict__ perm,
                                                                   const int *__restrict__ off_t, Geom g,
@@ -1539,57 +1538,86 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
   extern __shared__ unsigned char smem_raw[];
   FT *ext = reinterpret_cast<FT *>(smem_raw);
   const int tid = threadIdx.x;
+  // block = SY x SZ spread tiles along y and z (fewer at the top of an axis
+  // with an odd tile count)
+  const int nsy = (g.nt[1] + SY - 1) / SY;
   int t = blockIdx.x;
   const int tx = t % g.nt[0];
   t /= g.nt[0];
-  const int ty = t % g.nt[1];
-  const int tz = t / g.nt[1];
-  const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
-  const int E0 = g.T[0] + P - 1, E1 = g.T[1] + P - 1, E2 = g.T[2] + P - 1;
+  const int ty0 = SY * (t % nsy);
+  const int tz0 = SZ * (t / nsy);
+  const int nys = min(SY, g.nt[1] - ty0), nzs = min(SZ, g.nt[2] - tz0);
+  const int t0[3] = {tx * g.T[0], ty0 * g.T[1], tz0 * g.T[2]};
+  const int E0 = g.T[0] + P - 1, E1 = nys * g.T[1] + P - 1, E2 = nzs * g.T[2] + P - 1;
   const int e0x = t0[0] - P / 2 + 1, e0y = t0[1] - P / 2 + 1, e0z = t0[2] - P / 2 + 1;
-  const int nrow = E1 * E2;
   {
-    // rows (iy, iz) of E0 contiguous points: lane ix of a 32-lane group;
-    // eight rows' loads are issued before any is written to LDS
+    // the block's region plus halo, as one flat index over (z, y, x): eight
+    // loads in flight per lane before any is written to LDS; no wrapping
+    // arithmetic when the region lies inside the grid
     constexpr int kB = 8;
-    const int ix = tid & 31;
-    const int gx = wrapi(e0x + ix, g.M[0]);
-    const float inv_e1 = 1.0f / (float)E1;
-    const int step = blockDim.x >> 5;
-    for (int r0 = tid >> 5; r0 < nrow; r0 += kB * step) {
-      using V = pod_t<FT>;
-      const V *fsrc = reinterpret_cast<const V *>(field);
-      V *edst = reinterpret_cast<V *>(ext);
+    const int E01 = E0 * E1, nel = E01 * E2;
+    const float i01 = 1.0f / (float)E01, i0 = 1.0f / (float)E0;
+    const bool inner = e0x >= 0 && e0y >= 0 && e0z >= 0 && e0x + E0 <= g.M[0] && e0y + E1 <= g.M[1] &&
+                       e0z + E2 <= g.M[2];
+    using V = pod_t<FT>;
+    const V *fsrc = reinterpret_cast<const V *>(field);
+    V *edst = reinterpret_cast<V *>(ext);
+    for (int eb = tid; eb < nel; eb += kB * blockDim.x) {
       V v[kB];
 #pragma unroll
       for (int k = 0; k < kB; ++k) {
-        const int r = r0 + k * step;
+        const int e = eb + k * blockDim.x;
         v[k] = V{};
-        if (r < nrow && ix < E0) {
-          const int iz = (int)(((float)r + 0.5f) * inv_e1);
-          const int iy = r - iz * E1;
-          const int gy = wrapi(e0y + iy, g.M[1]), gz = wrapi(e0z + iz, g.M[2]);
+        if (e < nel) {
+          const int iz = (int)(((float)e + 0.5f) * i01);
+          const int rem = e - iz * E01;
+          const int iy = (int)(((float)rem + 0.5f) * i0);
+          const int ix = rem - iy * E0;
+          int gx = e0x + ix, gy = e0y + iy, gz = e0z + iz;
+          if (!inner) {
+            gx = wrapi(gx, g.M[0]);
+            gy = wrapi(gy, g.M[1]);
+            gz = wrapi(gz, g.M[2]);
+          }
           v[k] = fsrc[((size_t)gz * g.M[1] + gy) * g.M[0] + gx];
         }
       }
 #pragma unroll
       for (int k = 0; k < kB; ++k) {
-        const int r = r0 + k * step;
-        if (r < nrow && ix < E0) edst[r * E0 + ix] = v[k];
+        const int e = eb + k * blockDim.x;
+        if (e < nel) edst[e] = v[k];
       }
     }
   }
   __syncthreads();
-  const int tile = blockIdx.x;
-  const int a0 = off_t[tile * kTileBins], a1 = off_t[tile * kTileBins + kTileBins];
+  // the block's particles: the sorted ranges of its spread tiles, end to end
+  int rs[SY * SZ], rc[SY * SZ + 1];
+  rc[0] = 0;
+#pragma unroll
+  for (int sb = 0; sb < SY * SZ; ++sb) {
+    const int ya = sb % SY, zb = sb / SY;
+    int n = 0;
+    rs[sb] = 0;
+    if (ya < nys && zb < nzs) {
+      const int tile = ((tz0 + zb) * g.nt[1] + ty0 + ya) * g.nt[0] + tx;
+      rs[sb] = off_t[tile * kTileBins];
+      n = off_t[tile * kTileBins + kTileBins] - rs[sb];
+    }
+    rc[sb + 1] = rc[sb] + n;
+  }
+  const int ntot = rc[SY * SZ];
   const int sub = tid & (kGatherLanes - 1);
   // every lane of a wave runs the same number of iterations (the shuffles
   // below need all four lanes of a particle); lanes past the end idle
-  const int npass = (a1 - a0 + (blockDim.x / kGatherLanes) - 1) / (blockDim.x / kGatherLanes);
+  const int npass = (ntot + (blockDim.x / kGatherLanes) - 1) / (blockDim.x / kGatherLanes);
   for (int it = 0; it < npass; ++it) {
-    const int j = a0 + it * (blockDim.x / kGatherLanes) + (tid / kGatherLanes);
-    const bool live = j < a1;
-    const real4<R> v = part[live ? j : a0];
+    const int jv = it * (blockDim.x / kGatherLanes) + (tid / kGatherLanes);
+    const bool live = jv < ntot;
+    int sb = 0;
+#pragma unroll
+    for (int k = 1; k < SY * SZ; ++k) sb += jv >= rc[k] ? 1 : 0;
+    const int j = live ? rs[sb] + (jv - rc[sb]) : rs[0];
+    const real4<R> v = part[live ? j : 0];
     int l[3];
     R wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
     {
@@ -2205,8 +2233,8 @@ static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
                        (const real4<R> *)w.part_t, w.off_t, (const int *)w.runs, w.nruns, g, (R *)w.grid);
 }
 template <typename FT, int P>
-static size_t gather_tile_lds(const Geom &g) {
-  return (size_t)(g.T[0] + P - 1) * (g.T[1] + P - 1) * (g.T[2] + P - 1) * sizeof(FT);
+static size_t gather_tile_lds(const Geom &g, int sy, int sz) {
+  return (size_t)(g.T[0] + P - 1) * (sy * g.T[1] + P - 1) * (sz * g.T[2] + P - 1) * sizeof(FT);
 }
 // Gather kinds: ik forces and potentials from the interleaved (E, psi) grid;
 // gradient form (forces -dE/dr or the adjoint dE/dr, scaled by gs, and the
@@ -2215,9 +2243,19 @@ static size_t gather_tile_lds(const Geom &g) {
 enum GatherKind { kGatherIk = 0, kGatherGrad4 = 1, kGatherGradScalar = 2 };
 template <typename R, int P, bool GRAD, typename FT>
 static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R ss, R *vo, R *so) {
-  const size_t lds = gather_tile_lds<FT, P>(g);
+  // a potential-only grid stages 2 x 2 spread tiles (y, z) per block (less
+  // halo per point, more particles per block); the interleaved fields one
+  const size_t lds2 = gather_tile_lds<FT, P>(g, 2, 2);
+  if (sizeof(FT) == sizeof(R) && lds2 <= 65536) {
+    const int nb = g.nt[0] * ((g.nt[1] + 1) / 2) * ((g.nt[2] + 1) / 2);
+    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2>), dim3(nb), dim3(kGatherTileBlock), lds2, st,
+                       (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
+                       so);
+    return;
+  }
+  const size_t lds = gather_tile_lds<FT, P>(g, 1, 1);
   if (lds <= 65536) {
-    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
+    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 1, 1>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
                        so);
     return;
