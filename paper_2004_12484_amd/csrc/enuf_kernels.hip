@@ -1514,7 +1514,8 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
 // sums are combined with lane shuffles, so a tile of 64 particles keeps all
 // 256 lanes busy.  Used when
 // the staged tile fits the LDS budget; same outputs as k_gather.
-constexpr int kGatherLanes = 4;  // lanes per particle in k_gather_tile
+constexpr int kGatherLanes = 4;     // lanes per particle, one spread tile per workgroup
+constexpr int kGatherLanesBig = 2;  // lanes per particle, 2 x 2 spread tiles per workgroup
 
 // b ? y : x as a bit blend, so that picking between two register values is
 // never turned into an indexed load from a stack copy of the array
@@ -1528,7 +1529,7 @@ __device__ __forceinline__ double pick(int b, double x, double y) {
                                           ((unsigned long long)__double_as_longlong(y) & m)));
 }
 
-template <typename R, int P, bool GRAD, typename FT, int SY, int SZ>
+template <typename R, int P, bool GRAD, typename FT, int SY, int SZ, int KL>
 __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
                                                                   const int *__restrict__ perm,
                                                                   const int *__restrict__ off_t, Geom g,
@@ -1606,13 +1607,15 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
     rc[sb + 1] = rc[sb] + n;
   }
   const int ntot = rc[SY * SZ];
-  const int sub = tid & (kGatherLanes - 1);
+  const int sub = tid & (KL - 1);
   // every lane of a wave runs the same number of iterations (the shuffles
-  // below need all four lanes of a particle); lanes past the end idle
-  const int npass = (ntot + (blockDim.x / kGatherLanes) - 1) / (blockDim.x / kGatherLanes);
+  // below need all KL lanes of a particle); lanes past the end idle, waves
+  // past the end skip
+  const int npass = (ntot + (blockDim.x / KL) - 1) / (blockDim.x / KL);
   for (int it = 0; it < npass; ++it) {
-    const int jv = it * (blockDim.x / kGatherLanes) + (tid / kGatherLanes);
+    const int jv = it * (blockDim.x / KL) + (tid / KL);
     const bool live = jv < ntot;
+    if (!__any(live)) continue;
     int sb = 0;
 #pragma unroll
     for (int k = 1; k < SY * SZ; ++k) sb += jv >= rc[k] ? 1 : 0;
@@ -1632,27 +1635,30 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       if (GRAD) bspline_d<R, P>(v.z - fl, wz, dz); else bspline<R, P>(v.z - fl, wz);
     }
     R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
-    // this lane's (z, y) rows: z = za + 2m, y = yb + 2n (za, yb = the lane's
-    // bits), P^2/4 rows per lane; its z and y weights are picked once so the
-    // row loop indexes them statically
-    constexpr int H = P / 2;
-    const int za = sub >> 1, yb = sub & 1;
-    R mwz[H], mdz[H], mwy[H], mdy[H];
+    // this lane's (z, y) rows: with four lanes z = za + 2m, y = yb + 2n (za,
+    // yb = the lane's bits), with two z = za + 2m and every y, with one every
+    // row; its z and y weights are picked once so the row loop indexes them
+    // statically
+    constexpr int ZS = KL >= 2 ? 2 : 1, YS = KL == 4 ? 2 : 1;
+    constexpr int ZN = P / ZS, YN = P / YS;
+    const int za = KL == 4 ? sub >> 1 : (KL == 2 ? sub : 0), yb = KL == 4 ? sub & 1 : 0;
+    R mwz[ZN], mdz[ZN], mwy[YN], mdy[YN];
 #pragma unroll
-    for (int m = 0; m < H; ++m) {
-      mwz[m] = pick(za, wz[2 * m], wz[2 * m + 1]);
-      mwy[m] = pick(yb, wy[2 * m], wy[2 * m + 1]);
-      if (GRAD) {
-        mdz[m] = pick(za, dz[2 * m], dz[2 * m + 1]);
-        mdy[m] = pick(yb, dy[2 * m], dy[2 * m + 1]);
-      }
+    for (int m = 0; m < ZN; ++m) {
+      mwz[m] = ZS == 2 ? pick(za, wz[2 * m], wz[2 * m + 1]) : wz[m];
+      if (GRAD) mdz[m] = ZS == 2 ? pick(za, dz[2 * m], dz[2 * m + 1]) : dz[m];
+    }
+#pragma unroll
+    for (int m = 0; m < YN; ++m) {
+      mwy[m] = YS == 2 ? pick(yb, wy[2 * m], wy[2 * m + 1]) : wy[m];
+      if (GRAD) mdy[m] = YS == 2 ? pick(yb, dy[2 * m], dy[2 * m + 1]) : dy[m];
     }
     const FT *base = ext + ((l[2] + za) * E1 + l[1] + yb) * E0 + l[0];
 #pragma unroll
-    for (int mz = 0; mz < H; ++mz) {
+    for (int mz = 0; mz < ZN; ++mz) {
 #pragma unroll
-      for (int my = 0; my < H; ++my) {
-        const FT *row = base + (2 * mz * E1 + 2 * my) * E0;
+      for (int my = 0; my < YN; ++my) {
+        const FT *row = base + (ZS * mz * E1 + YS * my) * E0;
         // x sums of the row first, then the row's z-y weight
         if constexpr (!GRAD) {
           R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -1686,7 +1692,7 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       }
     }
 #pragma unroll
-    for (int o = 1; o < kGatherLanes; o <<= 1) {
+    for (int o = 1; o < KL; o <<= 1) {
       a0s += __shfl_xor(a0s, o, 64);
       a1s += __shfl_xor(a1s, o, 64);
       a2s += __shfl_xor(a2s, o, 64);
@@ -2248,14 +2254,14 @@ static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pre
   const size_t lds2 = gather_tile_lds<FT, P>(g, 2, 2);
   if (sizeof(FT) == sizeof(R) && lds2 <= 65536) {
     const int nb = g.nt[0] * ((g.nt[1] + 1) / 2) * ((g.nt[2] + 1) / 2);
-    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2>), dim3(nb), dim3(kGatherTileBlock), lds2, st,
+    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2, kGatherLanesBig>), dim3(nb), dim3(kGatherTileBlock), lds2, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
                        so);
     return;
   }
   const size_t lds = gather_tile_lds<FT, P>(g, 1, 1);
   if (lds <= 65536) {
-    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 1, 1>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
+    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 1, 1, kGatherLanes>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
                        so);
     return;
