@@ -906,7 +906,6 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
   const int ty = t % g.nt[1];
   const int tz = t / g.nt[1];
   const int t0[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
-  for (int e = tid; e < 32 * kSpreadLd; e += blockDim.x) (&E[0][0])[e] = 0.0f;
   tile_runs(off_t, runs, nruns, g, tx, ty, tz, rstart, rpre);
   const int total = rpre[nruns];
   int qe;
@@ -946,9 +945,15 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
       }
       qv = v.w * qscale;
     }
-    // deterministic compaction of the hits into columns 0 .. ns-1
+    // deterministic compaction of the hits into columns 0 .. ns-1; the
+    // columns up to the next multiple of 16 (read by the last k-step) are
+    // zeroed, so no stale LDS word ever enters a product
     int ns;
     const int slot = block_exscan_int(hit ? 1 : 0, &ns);
+    {
+      const int npad = ((ns + 15) & ~15) - ns;
+      for (int e = tid; e < 32 * npad; e += blockDim.x) E[e / npad][ns + e % npad] = 0.0f;
+    }
     if (hit) {
 #pragma unroll
       for (int r = 0; r < 32; ++r) E[r][slot] = 0.0f;
