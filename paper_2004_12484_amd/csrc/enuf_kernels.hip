@@ -1767,6 +1767,31 @@ __device__ __forceinline__ unsigned long long cut_limit(double rc2) {
   return (unsigned long long)__double_as_longlong(rc2) - 1ull;
 }
 
+// Constants of the pair sum, formed once on the host (double divisions are
+// costly per thread).  bg times the total charge is the background
+// potential; self times q_i the self potential.
+template <typename R>
+struct PairConst {
+  R L[3], iL[3], rc2, al, al2, c2a;
+  double bg, self;
+};
+template <typename R>
+static PairConst<R> pair_const(const Geom &g) {
+  const double pi = 3.14159265358979323846, sqpi = 1.7724538509055160272981674833411;
+  PairConst<R> c;
+  for (int d = 0; d < 3; ++d) {
+    c.L[d] = (R)g.L[d];
+    c.iL[d] = (R)(1.0 / g.L[d]);
+  }
+  c.rc2 = (R)(g.rc * g.rc);
+  c.al = (R)g.alpha;
+  c.al2 = (R)(g.alpha * g.alpha);
+  c.c2a = (R)(2.0 * g.alpha / sqpi);
+  c.bg = -g.ke * pi / (g.L[0] * g.L[1] * g.L[2] * g.alpha * g.alpha);
+  c.self = -2.0 * g.ke * g.alpha / sqpi;
+  return c;
+}
+
 // candidates staged per chunk: 12 KB of LDS in either precision
 template <typename R>
 constexpr int pair_chunk() { return sizeof(R) == 4 ? 768 : 384; }
@@ -1775,8 +1800,8 @@ template <typename R, int MODE, bool MINIMG>
 __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict__ part,
                                                      const int *__restrict__ perm,
                                                      const int *__restrict__ off_c, Geom g,
-                                                     const double *__restrict__ scal, R gscale,
-                                                     R *__restrict__ out_vec, R *__restrict__ out_sca,
+                                                     const double *__restrict__ scal, PairConst<R> pc,
+                                                     R gscale, R *__restrict__ out_vec, R *__restrict__ out_sca,
                                                      double *rpart) {
   constexpr int CH = pair_chunk<R>();
   __shared__ real4<R> cand[CH];
@@ -1833,14 +1858,13 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
   __syncthreads();
   const int ncand = rp[27];
   const int h0 = hrange[0], h1 = hrange[1];  // all active particles of the cell
-  const R L0 = (R)g.L[0], L1 = (R)g.L[1], L2 = (R)g.L[2];
-  const R iL0 = (R)(1.0 / g.L[0]), iL1 = (R)(1.0 / g.L[1]), iL2 = (R)(1.0 / g.L[2]);
-  const R rc2 = (R)(g.rc * g.rc);
-  const R al = (R)g.alpha, al2 = (R)(g.alpha * g.alpha);
-  const R c2a = (R)(2.0 * g.alpha / 1.7724538509055160272981674833411);
-  const double V = g.L[0] * g.L[1] * g.L[2];
-  const double phi_bg = -g.ke * 3.14159265358979323846 * scal[0] / (V * g.alpha * g.alpha);
-  const double c_self = -2.0 * g.ke * g.alpha / 1.7724538509055160272981674833411;
+  const R L0 = pc.L[0], L1 = pc.L[1], L2 = pc.L[2];
+  const R iL0 = pc.iL[0], iL1 = pc.iL[1], iL2 = pc.iL[2];
+  const R rc2 = pc.rc2;
+  const R al = pc.al, al2 = pc.al2;
+  const R c2a = pc.c2a;
+  const double phi_bg = pc.bg * scal[0];
+  const double c_self = pc.self;
   double e = 0.0;
 
   for (int hb = h0; hb < h1; hb += blockDim.x) {
@@ -2389,10 +2413,10 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   // pair
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 0, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.rpart);
   else
     hipLaunchKernelGGL((k_pair<R, 0, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, R(1), F, phi, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.rpart);
   ENUF_TRY(hipGetLastError());
   mark(8);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, (const double *)w.kpart, P.zblocks,
@@ -2415,10 +2439,10 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
   ENUF_TRY(hipGetLastError());
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 1, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.rpart);
   else
     hipLaunchKernelGGL((k_pair<R, 1, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, (R)gscale, dEdx, dEdq, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.rpart);
   return hipGetLastError();
 }
 
