@@ -126,6 +126,11 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
     for (int d = 1; d < 3; ++d) if (g.nc[d] > g.nc[dm]) dm = d;
     g.nc[dm] = std::max(1, g.nc[dm] / 2);
   }
+  for (int d = 0; d < 3; ++d) {
+    g.iL[d] = 1.0 / g.L[d];
+    g.mL[d] = g.M[d] / g.L[d];
+    g.cL[d] = g.nc[d] / g.L[d];
+  }
   g.ntiles = g.nt[0] * g.nt[1] * g.nt[2];
   g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
   g.p = p;

@@ -41,6 +41,9 @@ struct Geom {
   int p;           // window stencil width
   int n;           // particles
   double L[3];     // box
+  double iL[3];    // 1 / L, M / L, nc / L (formed once on the host)
+  double mL[3];
+  double cL[3];
   double alpha, rc, ke;
 };
 

@@ -255,8 +255,8 @@ template <typename R>
 __device__ __forceinline__ void particle_coords(const R (&p3)[3], const Geom &g, R (&xw)[3], R (&sg)[3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    xw[d] = wrap_pos(p3[d], R(g.L[d]), R(1.0 / g.L[d]));
-    sg[d] = grid_coord(xw[d], R(g.M[d] / g.L[d]), g.M[d]);
+    xw[d] = wrap_pos(p3[d], R(g.L[d]), R(g.iL[d]));
+    sg[d] = grid_coord(xw[d], R(g.mL[d]), g.M[d]);
   }
 }
 
@@ -269,7 +269,7 @@ __device__ __forceinline__ void particle_keys(const R (&xw)[3], const R (&sg)[3]
     const int gi = (int)sg[d];
     tix[d] = gi / g.T[d];
     dig[d] = spill_digit(gi - tix[d] * g.T[d], g.T[d], g.p);
-    const int ci = (int)(xw[d] * R(g.nc[d] / g.L[d]));
+    const int ci = (int)(xw[d] * R(g.cL[d]));
     cix[d] = ci < g.nc[d] ? ci : g.nc[d] - 1;
   }
   const int nt = neutral ? 1 : 0;
@@ -1504,9 +1504,9 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
   } else {
     if (vec_out) {
       const R c = gscale * pref * qi;
-      vec_out[3 * i] = c * R(g.M[0] / g.L[0]) * a0;
-      vec_out[3 * i + 1] = c * R(g.M[1] / g.L[1]) * a1;
-      vec_out[3 * i + 2] = c * R(g.M[2] / g.L[2]) * a2;
+      vec_out[3 * i] = c * R(g.mL[0]) * a0;
+      vec_out[3 * i + 1] = c * R(g.mL[1]) * a1;
+      vec_out[3 * i + 2] = c * R(g.mL[2]) * a2;
     }
     if (sca_out) sca_out[i] = sscale * pref * a3;
   }
@@ -1716,9 +1716,9 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
     } else {
       if (vec_out) {
         const R c = gscale * pref * qi;
-        vec_out[3 * i] = c * R(g.M[0] / g.L[0]) * a0s;
-        vec_out[3 * i + 1] = c * R(g.M[1] / g.L[1]) * a1s;
-        vec_out[3 * i + 2] = c * R(g.M[2] / g.L[2]) * a2s;
+        vec_out[3 * i] = c * R(g.mL[0]) * a0s;
+        vec_out[3 * i + 1] = c * R(g.mL[1]) * a1s;
+        vec_out[3 * i + 2] = c * R(g.mL[2]) * a2s;
       }
       if (sca_out) sca_out[i] = sscale * pref * a3s;
     }
@@ -1781,7 +1781,7 @@ static PairConst<R> pair_const(const Geom &g) {
   PairConst<R> c;
   for (int d = 0; d < 3; ++d) {
     c.L[d] = (R)g.L[d];
-    c.iL[d] = (R)(1.0 / g.L[d]);
+    c.iL[d] = (R)g.iL[d];
   }
   c.rc2 = (R)(g.rc * g.rc);
   c.al = (R)g.alpha;
