@@ -181,8 +181,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   ok = ok && need(dalloc(c, &w.counts, 4));
   ok = ok && need(dalloc(c, &w.scal, 4));
   ok = ok && need(dalloc(c, &w.qpart, (size_t)4 * sp.nblk));
-  ok = ok && need(dalloc(c, &w.kpart, (size_t)enuf::nblk_z(g, precision == ENUF_FP64)));
-  ok = ok && need(dalloc(c, &w.rpart, (size_t)enuf::nblk_pair(g)));
+  ok = ok && need(dalloc(c, &w.eslot, (size_t)2 * enuf::kESlots));
   ok = ok && need(dalloc(c, (unsigned char **)&w.grid, G * rs));
   ok = ok && need(dalloc(c, (unsigned char **)&w.spec, G / 2 * 2 * rs));
   ok = ok && need(dalloc(c, (unsigned char **)&w.fspec, 4 * (G / 2) * 2 * rs));
@@ -209,7 +208,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   e = hipMemcpy(w.tables, host.data(), ntab * rs, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(w.runs, runs, sizeof(int) * 5 * w.nruns, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(w.counts, 0, 4 * sizeof(int));
-  if (e == hipSuccess) e = hipMemset(w.kpart, 0, sizeof(double));
+  if (e == hipSuccess) e = hipMemset(w.eslot, 0, 2 * enuf::kESlots * sizeof(double));
   if (e != hipSuccess) {
     enuf_status s = hip_fail(nullptr, e, "workspace initialisation");
     free_all(c);

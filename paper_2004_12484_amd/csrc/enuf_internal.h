@@ -29,6 +29,7 @@ constexpr int kSortChunkMax = 2048;  // particles grouped in LDS at a time by th
 constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass
 constexpr int kSortFineRegs = 8;     // particles per thread held in registers by the fine pass
 constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)
+constexpr int kESlots = 64;    // energy partial sums per part (blocks add into slot = block mod 64)
 
 // Geometry and parameters, passed by value to kernels.
 struct Geom {
@@ -84,8 +85,7 @@ struct Work {
   int *counts = nullptr;    // [4]: active, charged, flags, spare
   double *scal = nullptr;   // [4]: Q, Q2, max abs(q), spare
   double *qpart = nullptr;  // [4*nblk] per counting block: sum q, sum q^2, max abs(q), charged count
-  double *kpart = nullptr;  // [nblk_z] partial reciprocal energies
-  double *rpart = nullptr;  // [ncells] partial real-space energies
+  double *eslot = nullptr;  // [2*kESlots] energy sums: reciprocal, then real space
   void *grid = nullptr;     // real [G]
   void *spec = nullptr;     // complex [G/2]
   void *fspec = nullptr;    // complex [4][G/2]
@@ -94,12 +94,9 @@ struct Work {
   size_t tab_off[kTabSlots] = {0};  // element offsets inside `tables`
 };
 
-// Launch-configuration numbers the host needs to size partial buffers.
-int nblk_pair(const Geom &g);
 // Runs of (neighbour tile offset, class range) a spread tile reads; returns
 // the number of runs and writes 5 ints per run into out (kMaxRuns capacity).
 int build_runs(const Geom &g, int *out);
-int nblk_z(const Geom &g, bool fp64);
 // Every transform pass of the grid fits one workgroup's LDS.
 bool fft_plans_fit(const Geom &g, bool fp64);
 

@@ -373,7 +373,10 @@ __global__ __launch_bounds__(1024) void k_sort_colscan(int *__restrict__ hist, S
 // grand total after the last bucket), the bin-offset terminators, the active
 // and charged counts and the charge sums.
 __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, SortPlan sp, int *off_t, int *off_c,
-                                                    const double *__restrict__ qpart, double *scal, int *counts) {
+                                                    const double *__restrict__ qpart, double *scal, int *counts,
+                                                    double *eslot) {
+  // the energy slots the transform and pair kernels add into
+  for (int i = threadIdx.x; i < 2 * kESlots; i += blockDim.x) eslot[i] = 0.0;
   __shared__ int carry;
   for (int seg = 0; seg < 2; ++seg) {
     const int lo = seg == 0 ? 0 : sp.nb[0] + 1, n = sp.nb[seg];
@@ -1282,7 +1285,7 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
                                                     const Cx<R> *__restrict__ tw_z, const R *__restrict__ sx,
                                                     const R *__restrict__ sy, const R *__restrict__ sz,
                                                     const R *__restrict__ kvx, const R *__restrict__ kvy,
-                                                    const R *__restrict__ kvz, double *kpart) {
+                                                    const R *__restrict__ kvz, double *eslot) {
   extern __shared__ unsigned char smem_raw[];
   const int n = 1 << lnz, nb = 1 << lnb, hx = 1 << lhx;
   const size_t inner = (size_t)hx * g.M[1];
@@ -1322,7 +1325,7 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
     __syncthreads();
   }
   const double tot = block_sum(en);
-  if (threadIdx.x == 0) kpart[blockIdx.x] = tot;
+  if (threadIdx.x == 0) atomicAdd(&eslot[blockIdx.x % kESlots], tot);
 }
 
 // x pass, inverse, nf components: bins 0 .. Mx/2-1 of each field (Nyquist
@@ -1802,7 +1805,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
                                                      const int *__restrict__ off_c, Geom g,
                                                      const double *__restrict__ scal, PairConst<R> pc,
                                                      R gscale, R *__restrict__ out_vec, R *__restrict__ out_sca,
-                                                     double *rpart) {
+                                                     double *eslot) {
   constexpr int CH = pair_chunk<R>();
   __shared__ real4<R> cand[CH];
   __shared__ R red[kPairBlock][4];
@@ -2007,7 +2010,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
   }
   if (MODE == 0) {
     const double tot = block_sum(e);
-    if (tid == 0) rpart[blockIdx.x] = tot;
+    if (tid == 0) atomicAdd(&eslot[kESlots + blockIdx.x % kESlots], tot);
   }
 }
 
@@ -2047,7 +2050,6 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *kpart, int nk, 
 // --------------------------------------------------------------------------
 // host side: tables and launch sequences
 // --------------------------------------------------------------------------
-int nblk_pair(const Geom &g) { return g.ncells; }
 
 size_t sort_stage_lds(const SortPlan &sp, int real_bytes) {
   const size_t nbm = std::max(sp.nb[0], sp.nb[1]);
@@ -2196,10 +2198,6 @@ bool fft_plans_fit(const Geom &g, bool fp64) {
   return true;
 }
 
-int nblk_z(const Geom &g, bool fp64) {
-  const size_t cs = fp64 ? 16 : 8;
-  return std::max(fft_plan(g, cs, 1).zblocks, std::max(fft_plan(g, cs, 3).zblocks, fft_plan(g, cs, 4).zblocks));
-}
 
 // table layout (in reals): [0] tw x-half (n=Mx/2) complex, [1] tw e^{-2pi i k/Mx}
 // k<Mx/2 complex, [2] tw y complex, [3] tw z complex, [4..6] influence
@@ -2363,7 +2361,7 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   // dead after staging and take the fine ranks)
   hipLaunchKernelGGL(k_sort_colscan, dim3((nbk + 63) / 64), dim3(1024), 0, st, w.hist, sp, w.bbase);
   hipLaunchKernelGGL(k_sort_base, dim3(1), dim3(1024), 0, st, w.bbase, sp, w.off_t, w.off_c,
-                     (const double *)w.qpart, w.scal, w.counts);
+                     (const double *)w.qpart, w.scal, w.counts, w.eslot);
   hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
                      x, q, g, sp, (const int *)w.key_t, (const int *)w.key_c, (const int *)w.hist,
                      (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c);
@@ -2387,7 +2385,7 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   // z fused: forward z, influence, energy, inverse z of the field spectra
   hipLaunchKernelGGL((k_z_fused<R>), dim3(P.zblocks), dim3(kBlock), P.lds_z, st, (const Cx<R> *)w.spec,
                      (Cx<R> *)w.fspec, g, P.lnz, P.lhx, P.lb_z, nfield, P.nfp, fbase, tw_z, sx, sy, sz, kvx, kvy,
-                     kvz, w.kpart);
+                     kvz, w.eslot);
   ENUF_TRY(hipGetLastError());
   mark(5);
   // inverse y (nfield components), inverse x c2r -> interleaved fields
@@ -2413,14 +2411,14 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   // pair
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 0, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.eslot);
   else
     hipLaunchKernelGGL((k_pair<R, 0, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.eslot);
   ENUF_TRY(hipGetLastError());
   mark(8);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, (const double *)w.kpart, P.zblocks,
-                     (const double *)w.rpart, nblk_pair(g), (const double *)w.scal, g, E);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, (const double *)w.eslot, kESlots,
+                     (const double *)(w.eslot + kESlots), kESlots, (const double *)w.scal, g, E);
   ENUF_TRY(hipGetLastError());
   mark(9);
   return hipSuccess;
@@ -2439,10 +2437,10 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
   ENUF_TRY(hipGetLastError());
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 1, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.eslot);
   else
     hipLaunchKernelGGL((k_pair<R, 1, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.rpart);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.eslot);
   return hipGetLastError();
 }
 
