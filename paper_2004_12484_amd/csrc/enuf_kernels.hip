@@ -1759,16 +1759,18 @@ __device__ __forceinline__ double exp_fast(double v) { return exp(v); }
 __device__ __forceinline__ float rsqrt_r(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_r(double v) { return 1.0 / sqrt(v); }
 
-// 0 < r2 < rc2 in one unsigned compare of the bit patterns (non-negative
-// floats order like their bits; r2 = 0 wraps to the largest value)
-__device__ __forceinline__ bool in_cut(float r2, unsigned lim) { return __float_as_uint(r2) - 1u < lim; }
-__device__ __forceinline__ bool in_cut(double r2, unsigned long long lim) {
-  return (unsigned long long)__double_as_longlong(r2) - 1ull < lim;
+// acc = 2 acc + (r2 < rc2): the compare's lane mask is the carry-in of an
+// add with carry, so marking a candidate costs two instructions
+__device__ __forceinline__ unsigned shift_in_lt(unsigned acc, float r2, float rc2) {
+  unsigned r;
+  asm("v_cmp_gt_f32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, %3, %3, vcc" : "=v"(r) : "v"(r2), "v"(rc2), "v"(acc)
+      : "vcc");
+  return r;
 }
-__device__ __forceinline__ unsigned cut_limit(float rc2) { return __float_as_uint(rc2) - 1u; }
-__device__ __forceinline__ unsigned long long cut_limit(double rc2) {
-  return (unsigned long long)__double_as_longlong(rc2) - 1ull;
+__device__ __forceinline__ unsigned shift_in_lt(unsigned acc, double r2, double rc2) {
+  return acc + acc + (r2 < rc2 ? 1u : 0u);
 }
+
 
 // Constants of the pair sum, formed once on the host (double divisions are
 // costly per thread).  bg times the total charge is the background
@@ -1937,29 +1939,37 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
         // marks the candidates inside the cutoff in a 64-bit mask, four per
         // unrolled step; pass 2 does the erfc/exp work for the marked ones
         // only, so lanes that miss do not idle through it
-        const auto lim = cut_limit(rc2);
         const int nmine = (nc - grp + Gh - 1) / Gh;
         for (int m0 = 0; m0 < nmine; m0 += 64) {
           const int n64 = min(64, nmine - m0);
           const int b0 = grp + Gh * m0;
+          // each half of the round shifts its marks in from the right
+          // (m = 2m + hit, an add with carry-in), then one bit reversal puts
+          // candidate k at bit k
           unsigned long long mask = 0ull;
-          int k = 0;
-#pragma unroll 1
-          for (; k + 4 <= n64; k += 4) {
-            unsigned nib = 0u;
-            const int a = b0 + Gh * k;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              R ddx, ddy, ddz;
-              sep(a + Gh * b, ddx, ddy, ddz);
-              nib |= in_cut(ddx * ddx + ddy * ddy + ddz * ddz, lim) ? (1u << b) : 0u;
+          for (int half = 0; half < 2; ++half) {
+            const int s0 = 32 * half, s1 = min(n64, s0 + 32);
+            if (s0 >= s1) break;
+            unsigned acc = 0u;
+            int k = s0;
+#pragma unroll 1
+            for (; k + 4 <= s1; k += 4) {
+              const int a = b0 + Gh * k;
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                R ddx, ddy, ddz;
+                sep(a + Gh * b, ddx, ddy, ddz);
+                acc = shift_in_lt(acc, ddx * ddx + ddy * ddy + ddz * ddz, rc2);
+              }
             }
-            mask |= (unsigned long long)nib << k;
-          }
-          for (; k < n64; ++k) {
-            R ddx, ddy, ddz;
-            sep(b0 + Gh * k, ddx, ddy, ddz);
-            if (in_cut(ddx * ddx + ddy * ddy + ddz * ddz, lim)) mask |= 1ull << k;
+            for (; k < s1; ++k) {
+              R ddx, ddy, ddz;
+              sep(b0 + Gh * k, ddx, ddy, ddz);
+              acc = shift_in_lt(acc, ddx * ddx + ddy * ddy + ddz * ddz, rc2);
+            }
+            acc = __builtin_bitreverse32(acc) >> (32 - (s1 - s0));
+            mask |= (unsigned long long)acc << s0;
           }
           while (mask) {
             const int b = __builtin_ctzll(mask);
@@ -1967,7 +1977,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
             R ddx, ddy, ddz;
             const R qj = sep(b0 + Gh * b, ddx, ddy, ddz);
             const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            const R ir = rsqrt_r(r2);
+            const R ir = r2 > R(0) ? rsqrt_r(r2) : R(0);  // r = 0 (itself) marked above, adds nothing
             const R r = r2 * ir;
             const R ex = exp_fast(-al2 * r2);
             const R ec = erfc_with_exp(al * r, ex) * ir;
