@@ -35,6 +35,10 @@ template <typename R> using real4 = typename V4<R>::T;
 
 template <typename R> struct Cx { R x, y; };
 
+// 1/x: the hardware reciprocal (1 ulp) in single precision, a division in double
+__device__ __forceinline__ float recip_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip_r(double x) { return 1.0 / x; }
+
 // plain register types for staging copies (no constructors, so arrays of
 // them stay in registers)
 template <typename T> struct PodOf { using type = T; };
@@ -1299,15 +1303,23 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
                  [=](int, int i, int f, Cx<R> v) { S[i * nb + f] = v; });
   __syncthreads();
   double en = 0.0;
-  for (int e = threadIdx.x; e < (n << lnb); e += blockDim.x) {
-    const int f = e & (nb - 1), kz = e >> lnb;
+  {
+    // a thread keeps one pencil f (blockDim is a multiple of nb), so its x
+    // and y factors are loaded once
+    const int f = threadIdx.x & (nb - 1);
     const int pidx = (int)p0 + f;
     const int kx = pidx & (hx - 1), ky = pidx >> lhx;
-    const R k2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky] + kvz[kz] * kvz[kz];
-    const R gv = k2 > R(0) ? sx[kx] * sy[ky] * sz[kz] / k2 : R(0);
-    const Cx<R> r = S[e];
-    en += (kx > 0 ? 2.0 : 1.0) * (double)gv * ((double)r.x * r.x + (double)r.y * r.y);
-    S[e] = Cx<R>{gv * r.x, gv * r.y};
+    const R kxy2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky];
+    const R sxy = sx[kx] * sy[ky];
+    const R wk = kx > 0 ? R(2) : R(1);  // the x half spectrum counts the other half too
+    for (int kz = threadIdx.x >> lnb; kz < n; kz += blockDim.x >> lnb) {
+      const int e = (kz << lnb) + f;
+      const R k2 = kxy2 + kvz[kz] * kvz[kz];
+      const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
+      const Cx<R> r = S[e];
+      en += (double)(wk * gv * (r.x * r.x + r.y * r.y));
+      S[e] = Cx<R>{gv * r.x, gv * r.y};
+    }
   }
   __syncthreads();
   for (int o0 = 0; o0 < nf; o0 += nfp) {
