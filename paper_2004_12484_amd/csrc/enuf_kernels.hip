@@ -1272,6 +1272,137 @@ __global__ __launch_bounds__(kBlock) void k_fft_y(Cx<R> *data, int ln, int linne
                   [=](int, int i, int f, Cx<R> v) { base[((size_t)i << linner) + f] = v; });
 }
 
+// One Stockham stage in place in LDS (element i of pencil f at X[i nb + f]):
+// every butterfly of the stage has its own thread (n / RAD * nb <= blockDim),
+// which reads its inputs, waits for the whole block, then writes its outputs.
+// Every thread of the block must call it.
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ void fft_stage_ip(int ln, int lns, int lnb, const Cx<R> *__restrict__ tw, Cx<R> *X) {
+  constexpr int LR = RAD == 16 ? 4 : (RAD == 8 ? 3 : 2);
+  const int lq = ln - LR;
+  const int lt = ln - lns - LR;
+  const int w = threadIdx.x;
+  const bool act = w < (1 << (lq + lnb));
+  const int f = w & ((1 << lnb) - 1);
+  const int j = (w >> lnb) & ((1 << lq) - 1);
+  const int k = j & ((1 << lns) - 1);
+  Cx<R> v[RAD];
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = X[((j + (r << lq)) << lnb) + f];
+    if (lns > 0) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        Cx<R> wr = tw[(r * k) << lt];
+        if (DIR > 0) wr = cconj(wr);
+        v[r] = cmul(v[r], wr);
+      }
+    }
+    dft<R, RAD, DIR>(v);
+  }
+  __syncthreads();
+  if (act) {
+    const int ob = ((j - k) << LR) + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) X[((ob + (r << lns)) << lnb) + f] = v[r];
+  }
+}
+
+// z pass for a single field from the potential spectrum (analytic forces),
+// lengths 128 and 256 (two stages): one LDS buffer of n x 16 pencils holds
+// the spectrum throughout (stages in place), so a block reads and writes
+// 128-byte rows and every thread owns a butterfly.  Same results as
+// k_z_fused with nf = 1, fbase = 3.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_z_psi(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec, Geom g,
+                                                  int lnz, int lhx, const Cx<R> *__restrict__ tw_z,
+                                                  const R *__restrict__ sx, const R *__restrict__ sy,
+                                                  const R *__restrict__ sz, const R *__restrict__ kvx,
+                                                  const R *__restrict__ kvy, const R *__restrict__ kvz,
+                                                  double *eslot) {
+  constexpr int lnb = 4, nb = 16;
+  extern __shared__ unsigned char smem_raw[];
+  Cx<R> *X = reinterpret_cast<Cx<R> *>(smem_raw);
+  const int n = 1 << lnz, hx = 1 << lhx;
+  const size_t inner = (size_t)hx * g.M[1];
+  const size_t p0 = (size_t)blockIdx.x << lnb;
+  const int L1 = lnz == 8 ? 4 : 3;  // second stage radix 16 (n = 256) or 8 (n = 128)
+  // forward: radix-16 stage from global memory into X, then the second stage in place
+  {
+    constexpr int LR = 4;
+    const int lq = lnz - LR;
+    const int w = threadIdx.x;
+    const bool act = w < (1 << (lq + lnb));
+    const int f = w & (nb - 1), j = (w >> lnb) & ((1 << lq) - 1);
+    Cx<R> v[16];
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = spec[(size_t)(j + (r << lq)) * inner + p0 + f];
+      dft<R, 16, -1>(v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) X[((j * 16 + r) << lnb) + f] = v[r];
+    }
+  }
+  __syncthreads();
+  if (L1 == 4) fft_stage_ip<R, 16, -1>(lnz, 4, lnb, tw_z, X);
+  else fft_stage_ip<R, 8, -1>(lnz, 4, lnb, tw_z, X);
+  __syncthreads();
+  double en = 0.0;
+  {
+    const int f = threadIdx.x & (nb - 1);
+    const int pidx = (int)p0 + f;
+    const int kx = pidx & (hx - 1), ky = pidx >> lhx;
+    const R kxy2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky];
+    const R sxy = sx[kx] * sy[ky];
+    const R wk = kx > 0 ? R(2) : R(1);
+    for (int kz = threadIdx.x >> lnb; kz < n; kz += blockDim.x >> lnb) {
+      const int e = (kz << lnb) + f;
+      const R k2 = kxy2 + kvz[kz] * kvz[kz];
+      const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
+      const Cx<R> r = X[e];
+      en += (double)(wk * gv * (r.x * r.x + r.y * r.y));
+      X[e] = Cx<R>{gv * r.x, gv * r.y};
+    }
+  }
+  __syncthreads();
+  // inverse: first stage in place, the second writes global memory
+  fft_stage_ip<R, 16, 1>(lnz, 0, lnb, tw_z, X);
+  __syncthreads();
+  {
+    const int LR = L1;
+    const int lq = lnz - LR;
+    const int lt = lnz - 4 - LR;
+    const int w = threadIdx.x;
+    const bool act = w < (1 << (lq + lnb));
+    const int f = w & (nb - 1), j = (w >> lnb) & ((1 << lq) - 1);
+    const int k = j & 15;
+    if (act) {
+      const int ob = ((j - k) << LR) + k;
+      if (L1 == 4) {
+        Cx<R> v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = X[((j + (r << lq)) << lnb) + f];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], cconj(tw_z[(r * k) << lt]));
+        dft<R, 16, 1>(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) fspec[(size_t)(ob + (r << 4)) * inner + p0 + f] = v[r];
+      } else {
+        Cx<R> v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = X[((j + (r << lq)) << lnb) + f];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], cconj(tw_z[(r * k) << lt]));
+        dft<R, 8, 1>(v);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) fspec[(size_t)(ob + (r << 4)) * inner + p0 + f] = v[r];
+      }
+    }
+  }
+  const double tot = block_sum(en);
+  if (threadIdx.x == 0) atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+}
+
 // z pass fused with the scaling and influence steps.  For each pencil
 // (kx, ky): forward transform along z; then for every mode n in the k-set
 //   g(n) = A(k) / c(n)^2,  A = exp(-k^2/4a^2)/k^2,  c = window transform,
@@ -2405,9 +2536,15 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   ENUF_TRY(hipGetLastError());
   mark(4);
   // z fused: forward z, influence, energy, inverse z of the field spectra
-  hipLaunchKernelGGL((k_z_fused<R>), dim3(P.zblocks), dim3(kBlock), P.lds_z, st, (const Cx<R> *)w.spec,
-                     (Cx<R> *)w.fspec, g, P.lnz, P.lhx, P.lb_z, nfield, P.nfp, fbase, tw_z, sx, sy, sz, kvx, kvy,
-                     kvz, w.eslot);
+  const int zp = hx * g.M[1];
+  if (analytic && sizeof(R) == 4 && (P.lnz == 7 || P.lnz == 8) && zp % 16 == 0)
+    hipLaunchKernelGGL((k_z_psi<R>), dim3(zp / 16), dim3(kBlock), (size_t)16 * sizeof(Cx<R>) << P.lnz, st,
+                       (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, P.lnz, P.lhx, tw_z, sx, sy, sz, kvx, kvy, kvz,
+                       w.eslot);
+  else
+    hipLaunchKernelGGL((k_z_fused<R>), dim3(P.zblocks), dim3(kBlock), P.lds_z, st, (const Cx<R> *)w.spec,
+                       (Cx<R> *)w.fspec, g, P.lnz, P.lhx, P.lb_z, nfield, P.nfp, fbase, tw_z, sx, sy, sz, kvx, kvy,
+                       kvz, w.eslot);
   ENUF_TRY(hipGetLastError());
   mark(5);
   // inverse y (nfield components), inverse x c2r -> interleaved fields
