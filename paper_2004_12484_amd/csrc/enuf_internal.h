@@ -19,7 +19,7 @@ constexpr int kMaxTilePts = kTileX * kTileY * kTileZ;
 constexpr int kClasses = 27;         // stencil spill classes per tile (3 digits: low/none/high)
 constexpr int kTileBins = 2 * kClasses;  // sort bins per tile: charged classes, then neutral
 constexpr int kMaxRuns = 256;        // neighbour (tile, class-range) runs read by one spread tile
-constexpr int kPairBlock = 256;      // threads per cell in the pair kernel
+constexpr int kPairBlock = 192;      // threads per cell in the pair kernel (27 staging teams of 7)
 constexpr int kSortBlock = 256;      // threads per block of the sort passes
 constexpr int kSortPer = 2048;       // particles per counting block (before the cap)
 constexpr int kSortMaxBlocks = 1024; // cap on counting blocks

@@ -2056,14 +2056,15 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
       const int nc = min(CH, ncand - c0);
       __syncthreads();
       {
-        // stage candidates c0 .. c0+nc-1: a team of 9 threads per neighbour
-        // cell copies that cell's part of the window, 9 consecutive particles
-        // per step (27 teams of 9 in a block of 256)
-        const int r = tid / 9, j0 = tid - 9 * (tid / 9);
+        // stage candidates c0 .. c0+nc-1: a team of TS threads per neighbour
+        // cell copies that cell's part of the window, TS consecutive
+        // particles per step (27 teams of TS = blockDim / 27)
+        constexpr int TS = kPairBlock / 27;
+        const int r = tid / TS, j0 = tid - TS * (tid / TS);
         if (r < 27) {
           const int a0 = max(0, c0 - rp[r]), a1 = min(rp[r + 1] - rp[r], c0 + nc - rp[r]);
           const R sx = rsh[r][0], sy = rsh[r][1], sz = rsh[r][2];
-          for (int k = a0 + j0; k < a1; k += 9) {
+          for (int k = a0 + j0; k < a1; k += TS) {
             const pod_t<real4<R>> v = *reinterpret_cast<const pod_t<real4<R>> *>(part + rs[r] + k);
             real4<R> u;
             u.x = v[0] + sx;
