@@ -1526,12 +1526,11 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_c2r4(const Cx<R> *__restrict__
       [=](int o, int i, int f, Cx<R> v) { res[(o * n + i) * ldp + f] = v; });
   __syncthreads();
   if constexpr (SCALAR) {
-    // one field: a plain real grid
-    R *dst = reinterpret_cast<R *>(field_out) + row0 * Mx;
-    for (int e = threadIdx.x; e < (nb * Mx); e += blockDim.x) {
-      const int xi = e & (Mx - 1), f = e >> (lnh + 1);
-      const Cx<R> v = res[(xi >> 1) * ldp + f];
-      dst[e] = (xi & 1) ? v.y : v.x;
+    // one field: a plain real grid; z_j holds the reals x_{2j}, x_{2j+1}
+    Cx<R> *dst = reinterpret_cast<Cx<R> *>(reinterpret_cast<R *>(field_out) + row0 * Mx);
+    for (int e = threadIdx.x; e < (nb << lnh); e += blockDim.x) {
+      const int j = e & (n - 1), f = e >> lnh;
+      dst[e] = res[j * ldp + f];
     }
     return;
   }
@@ -2338,7 +2337,7 @@ static FftPlan fft_plan(const Geom &g, size_t cs, int nf) {
   P.lds_z = zl(P.nfp, P.lb_z);
   P.zblocks = zp >> P.lb_z;
   auto c2r = [&](int lb) { return 2 * (size_t)nf * nh * pad_ld(lb) * cs; };
-  P.lb_c2r = pick(g.M[1] * g.M[2], c2r, 32768);
+  P.lb_c2r = pick(g.M[1] * g.M[2], c2r, 40960);  // 16 rows of 256 points (faster than 8 there; not for r2c)
   P.lds_c2r = c2r(P.lb_c2r);
   return P;
 }
