@@ -297,32 +297,50 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const R *__restrict__
   const long long i0 = (long long)blockIdx.x * sp.per;
   const int i1 = (int)min((long long)g.n, i0 + sp.per);
   double qs = 0.0, q2 = 0.0, qa = 0.0, nq = 0.0;
-  for (int i = (int)i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
-    const R qi = q[i];
-    const bool fin = isfinite(p3[0]) && isfinite(p3[1]) && isfinite(p3[2]) && isfinite(qi);
-    if (!fin) atomicOr(&counts[2], 1);
-    const bool active = fin && (qi != R(0) || all_active);
-    if (fin) {
-      qs += (double)qi;
-      q2 += (double)qi * (double)qi;
-      qa = fmax(qa, fabs((double)qi));
+  // four particles per thread per step: their loads are issued together
+  constexpr int U = 4;
+  for (int ib = (int)i0 + threadIdx.x; ib < i1; ib += U * blockDim.x) {
+    R px[U][3], pq[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = ib + u * blockDim.x;
+      if (i < i1) {
+        px[u][0] = x[3 * i];
+        px[u][1] = x[3 * i + 1];
+        px[u][2] = x[3 * i + 2];
+        pq[u] = q[i];
+      }
     }
-    if (active) {
-      R xw[3], sg[3];
-      particle_coords(p3, g, xw, sg);
-      int kt, kc;
-      particle_keys(xw, sg, qi == R(0), g, kt, kc);
-      key_t[i] = kt;
-      key_c[i] = kc;
-      atomicAdd(&cnt[kt >> sp.sh[0]], 1);
-      atomicAdd(&cnt[sp.nb[0] + (kc >> sp.sh[1])], 1);
-      if (qi != R(0)) nq += 1.0;
-    } else {
-      key_t[i] = -1;
-      key_c[i] = -1;
-      if (F) { F[3 * i] = R(0); F[3 * i + 1] = R(0); F[3 * i + 2] = R(0); }
-      if (phi) phi[i] = R(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = ib + u * blockDim.x;
+      if (i >= i1) break;
+      const R p3[3] = {px[u][0], px[u][1], px[u][2]};
+      const R qi = pq[u];
+      const bool fin = isfinite(p3[0]) && isfinite(p3[1]) && isfinite(p3[2]) && isfinite(qi);
+      if (!fin) atomicOr(&counts[2], 1);
+      const bool active = fin && (qi != R(0) || all_active);
+      if (fin) {
+        qs += (double)qi;
+        q2 += (double)qi * (double)qi;
+        qa = fmax(qa, fabs((double)qi));
+      }
+      if (active) {
+        R xw[3], sg[3];
+        particle_coords(p3, g, xw, sg);
+        int kt, kc;
+        particle_keys(xw, sg, qi == R(0), g, kt, kc);
+        key_t[i] = kt;
+        key_c[i] = kc;
+        atomicAdd(&cnt[kt >> sp.sh[0]], 1);
+        atomicAdd(&cnt[sp.nb[0] + (kc >> sp.sh[1])], 1);
+        if (qi != R(0)) nq += 1.0;
+      } else {
+        key_t[i] = -1;
+        key_c[i] = -1;
+        if (F) { F[3 * i] = R(0); F[3 * i + 1] = R(0); F[3 * i + 2] = R(0); }
+        if (phi) phi[i] = R(0);
+      }
     }
   }
   __syncthreads();
