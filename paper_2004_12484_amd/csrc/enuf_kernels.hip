@@ -359,34 +359,38 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const R *__restrict__
 }
 
 // Exclusive scan over the blocks of each bucket column of hist (in place);
-// the column total goes to the bucket's slot of bbase.  64 columns per
-// workgroup, 16 row groups of 64 lanes each.
+// the column total goes to the bucket's slot of bbase.  16 columns per
+// workgroup (64-byte row segments), 64 row groups of up to a few rows each,
+// the row group's values held in registers between the two passes.
 __device__ __forceinline__ int bucket_slot(const SortPlan &sp, int b) { return b < sp.nb[0] ? b : b + 1; }
 
-__global__ __launch_bounds__(1024) void k_sort_colscan(int *__restrict__ hist, SortPlan sp, int *__restrict__ bbase) {
-  __shared__ int part[16][64];
+constexpr int kColW = 16, kColG = 64, kColR = 16;  // columns, row groups, rows per group held
+
+__global__ __launch_bounds__(kColW * kColG) void k_sort_colscan(int *__restrict__ hist, SortPlan sp,
+                                                                int *__restrict__ bbase) {
+  __shared__ int part[kColG][kColW];
   const int nbk = sp.nb[0] + sp.nb[1];
-  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + lane;
-  const int rows = (sp.nblk + 15) / 16;
+  const int lane = threadIdx.x % kColW, rg = threadIdx.x / kColW;
+  const int col = blockIdx.x * kColW + lane;
+  const int rows = (sp.nblk + kColG - 1) / kColG;  // <= kColR: nblk <= kSortMaxBlocks
   const int r0 = rg * rows, r1 = min(sp.nblk, r0 + rows);
+  int v[kColR];
   int s = 0;
-  if (col < nbk) {
-#pragma unroll 8
-    for (int r = r0; r < r1; ++r) s += hist[(size_t)r * nbk + col];
+#pragma unroll
+  for (int k = 0; k < kColR; ++k) {
+    v[k] = (col < nbk && r0 + k < r1) ? hist[(size_t)(r0 + k) * nbk + col] : 0;
+    s += v[k];
   }
   part[rg][lane] = s;
   __syncthreads();
   int run = 0;
   for (int k = 0; k < rg; ++k) run += part[k][lane];
   if (col < nbk) {
-    if (rg == 15) bbase[bucket_slot(sp, col)] = run + s;
-#pragma unroll 8
-    for (int r = r0; r < r1; ++r) {
-      int *h = hist + (size_t)r * nbk + col;
-      const int v = *h;
-      *h = run;
-      run += v;
+    if (rg == kColG - 1) bbase[bucket_slot(sp, col)] = run + s;
+#pragma unroll
+    for (int k = 0; k < kColR; ++k) {
+      if (r0 + k < r1) hist[(size_t)(r0 + k) * nbk + col] = run;
+      run += v[k];
     }
   }
 }
@@ -399,6 +403,14 @@ __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, Sor
                                                     double *eslot) {
   // the energy slots the transform and pair kernels add into
   for (int i = threadIdx.x; i < 2 * kESlots; i += blockDim.x) eslot[i] = 0.0;
+  // per-block charge sums, loaded first so their latency overlaps the scans
+  double a = 0.0, b = 0.0, m = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < sp.nblk; i += blockDim.x) {
+    a += qpart[4 * i];
+    b += qpart[4 * i + 1];
+    m = fmax(m, qpart[4 * i + 2]);
+    c += qpart[4 * i + 3];
+  }
   __shared__ int carry;
   for (int seg = 0; seg < 2; ++seg) {
     const int lo = seg == 0 ? 0 : sp.nb[0] + 1, n = sp.nb[seg];
@@ -422,22 +434,35 @@ __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, Sor
     }
     __syncthreads();
   }
-  double a = 0.0, b = 0.0, m = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < sp.nblk; i += blockDim.x) {
-    a += qpart[4 * i];
-    b += qpart[4 * i + 1];
-    m = fmax(m, qpart[4 * i + 2]);
-    c += qpart[4 * i + 3];
+  // the four reductions in one exchange
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+    m = fmax(m, __shfl_down(m, o, 64));
+    c += __shfl_down(c, o, 64);
   }
-  a = block_sum(a);
-  b = block_sum(b);
-  m = block_max(m);
-  c = block_sum(c);
+  __shared__ double red4[16][4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red4[wv][0] = a;
+    red4[wv][1] = b;
+    red4[wv][2] = m;
+    red4[wv][3] = c;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    counts[1] = (int)c;
-    scal[0] = a;
-    scal[1] = b;
-    scal[2] = m;
+    double sa = 0.0, sb = 0.0, sm = 0.0, sc = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      sa += red4[k][0];
+      sb += red4[k][1];
+      sm = fmax(sm, red4[k][2]);
+      sc += red4[k][3];
+    }
+    counts[1] = (int)sc;
+    scal[0] = sa;
+    scal[1] = sb;
+    scal[2] = sm;
   }
 }
 
@@ -2530,7 +2555,8 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   mark(1);
   // sort: slots, bucket staging, fine sort per bucket (the key arrays are
   // dead after staging and take the fine ranks)
-  hipLaunchKernelGGL(k_sort_colscan, dim3((nbk + 63) / 64), dim3(1024), 0, st, w.hist, sp, w.bbase);
+  hipLaunchKernelGGL(k_sort_colscan, dim3((nbk + kColW - 1) / kColW), dim3(kColW * kColG), 0, st, w.hist, sp,
+                     w.bbase);
   hipLaunchKernelGGL(k_sort_base, dim3(1), dim3(1024), 0, st, w.bbase, sp, w.off_t, w.off_c,
                      (const double *)w.qpart, w.scal, w.counts, w.eslot);
   hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
