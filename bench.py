@@ -48,27 +48,29 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(w, rs, nq, nfield=3):
+def algorithmic_bytes(w, rs, nq, nfield, out_reals):
     """Algorithmic HBM bytes of each HBM-bound phase for one evaluation.
 
     rs = bytes per real; nq = active (charged) particles; G = grid points (the
-    half spectrum, Mx/2 x My x Mz complex, is also G reals); nfield = 3 field
-    spectra for forces (E_x, E_y, E_z).
+    half spectrum, Mx/2 x My x Mz complex, is also G reals); nfield = field
+    spectra transformed back (ik: E_x, E_y, E_z and, with potentials, psi;
+    analytic: psi alone); out_reals = reals per grid point of the real field
+    array the gather reads (ik: 4, interleaved; analytic: 1).
     spread:  read particles (4 reals) + write the grid once
     fft_fwd: x pass read G reals / write G; y pass read + write G
     influence_z: read G, write nfield x G
     fft_inv: y pass read + write nfield x G; x pass read nfield x G, write the
-             interleaved field array G x 4 reals
-    gather:  read particles (4 reals) + perm (4 B) + fields (G x 4 reals) and
-             write 3 force reals per particle
+             real field array G x out_reals
+    gather:  read particles (4 reals) + perm (4 B) + fields (G x out_reals)
+             and write 3 force reals per particle
     """
     G = int(np.prod(w.M))
     return {
         "spread": nq * 4 * rs + G * rs,
         "fft_fwd": 2 * G * rs + 2 * G * rs,
         "influence_z": G * rs + nfield * G * rs,
-        "fft_inv": 2 * nfield * G * rs + (nfield * G * rs + 4 * G * rs),
-        "gather": nq * (4 * rs + 4 + 3 * rs) + 4 * G * rs,
+        "fft_inv": 2 * nfield * G * rs + (nfield * G * rs + out_reals * G * rs),
+        "gather": nq * (4 * rs + 4 + 3 * rs) + out_reals * G * rs,
     }
 
 
@@ -248,9 +250,8 @@ def main():
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures a single GPU: this ENUF build has no multi-GPU path "
-              "(one GPU's throughput is the figure; DESIGN.md describes how it would shard).",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path, "
+              "and the figure it reports is one GPU's throughput.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -339,7 +340,9 @@ def main():
     acc = golden_check(w, Fh, float(Eh[0]), phi.double().cpu().numpy() if phi is not None else None)
 
     # roofline of the dominant phase
-    ab = algorithmic_bytes(w, rs, nq)
+    analytic = force_mode == "analytic"
+    ab = algorithmic_bytes(w, rs, nq, nfield=1 if analytic else (4 if phi is not None else 3),
+                           out_reals=1 if analytic else 4)
     dom = max(phases, key=phases.get)
     if dom in ab:
         achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
