@@ -131,65 +131,81 @@ __device__ __forceinline__ int wrapi(int i, int m) { return i < 0 ? i + m : (i >
 // with f the fractional part of the grid coordinate, the stencil points are
 // floor(s) - P/2 + 1 + j and their weights w[j] = M_P(f + P - 1 - j), using
 // M_1 = 1 on [0,1) and M_n(y) = (y M_{n-1}(y) + (n - y) M_{n-1}(y - 1))/(n-1).
-// Built in place for increasing order; v[k] holds M_n(f + k).
+//
+// Each weight is one polynomial piece of M_P, a polynomial of degree P - 1 in
+// f.  BsplinePoly runs the recursion at compile time on those pieces:
+// V_k(f) = (n-1)! M_n(f + k) has integer coefficients, with
+//   V^n_k = (f + k) V^{n-1}_k + (n - k - f) V^{n-1}_{k-1},
+// and c[j][m] = V^P_{P-1-j}[m] / (P-1)! is the coefficient of f^m in w[j].
+template <int P>
+struct BsplinePoly {
+  double c[P][P];
+  constexpr BsplinePoly() : c() {
+    long long v[P][P] = {};
+    v[0][0] = 1;
+    for (int n = 2; n <= P; ++n) {
+      long long u[P][P] = {};
+      for (int k = 0; k < n; ++k)
+        for (int m = 0; m < n; ++m) {
+          long long t = k * v[k][m] + (m > 0 ? v[k][m - 1] : 0);
+          if (k > 0) t += (n - k) * v[k - 1][m] - (m > 0 ? v[k - 1][m - 1] : 0);
+          u[k][m] = t;
+        }
+      for (int k = 0; k < P; ++k)
+        for (int m = 0; m < P; ++m) v[k][m] = u[k][m];
+    }
+    double fact = 1.0;
+    for (int i = 2; i < P; ++i) fact *= i;
+    for (int j = 0; j < P; ++j)
+      for (int m = 0; m < P; ++m) c[j][m] = (double)v[P - 1 - j][m] / fact;
+  }
+};
+
+// Weights by Horner's rule.  M_P(y) = M_P(P - y) gives w[P-1-j](f) =
+// w[j](1 - f), so only the pieces j >= P/2 are used, each in the variable in
+// which it vanishes at 0 (f for w[j], 1 - f for w[P-1-j]): the small weights
+// at the stencil's ends keep their relative accuracy.
 template <typename R, int P>
 __device__ __forceinline__ void bspline(R f, R (&w)[P]) {
-  R v[P];
-  v[0] = R(1);
+  constexpr BsplinePoly<P> C{};
+  const R u = R(1) - f;
 #pragma unroll
-  for (int n = 2; n <= P; ++n) {
-    const R inv = R(1) / R(n - 1);
-    v[n - 1] = (R(1) - f) * v[n - 2] * inv;
+  for (int j = P / 2; j < P; ++j) {
+    R a = R(C.c[j][P - 1]), b = a;
 #pragma unroll
-    for (int k = n - 2; k >= 1; --k) {
-      const R y = f + R(k);
-      v[k] = (y * v[k] + (R(n) - y) * v[k - 1]) * inv;
+    for (int m = P - 2; m >= 0; --m) {
+      a = fma(a, f, R(C.c[j][m]));
+      b = fma(b, u, R(C.c[j][m]));
     }
-    v[0] = f * v[0] * inv;
+    w[j] = a;
+    w[P - 1 - j] = b;
   }
-#pragma unroll
-  for (int j = 0; j < P; ++j) w[j] = v[P - 1 - j];
 }
 
-// Same, plus the derivative of each weight with respect to s:
-// M_P'(y) = M_{P-1}(y) - M_{P-1}(y - 1).
+// Same, plus the derivative of each weight with respect to s (= d/df), from
+// the differentiated pieces (d/df of w[j](1 - f) is -w[j]'(1 - f)).
 template <typename R, int P>
 __device__ __forceinline__ void bspline_d(R f, R (&w)[P], R (&dw)[P]) {
-  R v[P];
-  v[0] = R(1);
+  constexpr BsplinePoly<P> C{};
+  const R u = R(1) - f;
 #pragma unroll
-  for (int n = 2; n <= P - 1; ++n) {
-    const R inv = R(1) / R(n - 1);
-    v[n - 1] = (R(1) - f) * v[n - 2] * inv;
+  for (int j = P / 2; j < P; ++j) {
+    R a = R(C.c[j][P - 1]), b = a;
+    R da = R((P - 1) * C.c[j][P - 1]), db = da;
 #pragma unroll
-    for (int k = n - 2; k >= 1; --k) {
-      const R y = f + R(k);
-      v[k] = (y * v[k] + (R(n) - y) * v[k - 1]) * inv;
+    for (int m = P - 2; m >= 0; --m) {
+      a = fma(a, f, R(C.c[j][m]));
+      b = fma(b, u, R(C.c[j][m]));
+      if (m >= 1) {
+        da = fma(da, f, R(m * C.c[j][m]));
+        db = fma(db, u, R(m * C.c[j][m]));
+      }
     }
-    v[0] = f * v[0] * inv;
+    w[j] = a;
+    w[P - 1 - j] = b;
+    dw[j] = da;
+    dw[P - 1 - j] = -db;
   }
-  // order P-1 values u[k] = M_{P-1}(f + k), k < P-1
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    const int k1 = P - 1 - j, k2 = P - 2 - j;  // u(k) = v[k] for 0 <= k <= P-2, else 0
-    R a = R(0), b = R(0);
-    if (k1 <= P - 2) a = v[k1];
-    if (k2 >= 0) b = v[k2];
-    dw[j] = a - b;
-  }
-  {
-    const int n = P;
-    const R inv = R(1) / R(n - 1);
-    v[n - 1] = (R(1) - f) * v[n - 2] * inv;
-#pragma unroll
-    for (int k = n - 2; k >= 1; --k) {
-      const R y = f + R(k);
-      v[k] = (y * v[k] + (R(n) - y) * v[k - 1]) * inv;
-    }
-    v[0] = f * v[0] * inv;
-  }
-#pragma unroll
-  for (int j = 0; j < P; ++j) w[j] = v[P - 1 - j];
 }
 
 // --------------------------------------------------------------------------
