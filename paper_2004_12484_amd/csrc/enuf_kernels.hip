@@ -1865,6 +1865,9 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
     const FT *base = ext + ((l[2] + za) * E1 + l[1] + yb) * E0 + l[0];
 #pragma unroll
     for (int mz = 0; mz < ZN; ++mz) {
+      // gradient form: per z plane, y sums of the row sums (sum_y w_y sw,
+      // sum_y w'_y sw, sum_y w_y sd), then the plane's z weights
+      R tw = 0, tdy = 0, td = 0;
 #pragma unroll
       for (int my = 0; my < YN; ++my) {
         const FT *row = base + (ZS * mz * E1 + YS * my) * E0;
@@ -1892,12 +1895,16 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
             sw += wx[jx] * psi;
             sd += dx[jx] * psi;
           }
-          const R wzy = mwz[mz] * mwy[my];
-          a0s += wzy * sd;
-          a1s += (mwz[mz] * mdy[my]) * sw;
-          a2s += (mdz[mz] * mwy[my]) * sw;
-          a3s += wzy * sw;
+          tw += mwy[my] * sw;
+          tdy += mdy[my] * sw;
+          td += mwy[my] * sd;
         }
+      }
+      if constexpr (GRAD) {
+        a0s += mwz[mz] * td;
+        a1s += mwz[mz] * tdy;
+        a2s += mdz[mz] * tw;
+        a3s += mwz[mz] * tw;
       }
     }
 #pragma unroll
