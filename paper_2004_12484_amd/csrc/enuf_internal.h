@@ -24,6 +24,7 @@ constexpr int kSortBlock = 256;      // threads per block of the sort passes
 constexpr int kSortPer = 2048;       // particles per counting block (before the cap)
 constexpr int kSortMaxBlocks = 1024; // cap on counting blocks
 constexpr int kSortBuckets = 256;    // target buckets per order
+constexpr int kSortBucketsMax = 4096; // cap on the target for large systems (LDS of the count pass)
 constexpr int kSortFineLog = 12;     // at most 2^12 keys per bucket
 constexpr int kSortChunkMax = 2048;  // particles grouped in LDS at a time by the staging pass
 constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass

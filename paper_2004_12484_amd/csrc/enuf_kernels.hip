@@ -2286,9 +2286,13 @@ SortPlan sort_plan(const Geom &g, int real_bytes) {
   sp.per = (g.n + sp.nblk - 1) / sp.nblk;
   sp.nbins[0] = kTileBins * g.ntiles;
   sp.nbins[1] = 2 * g.ncells;
+  // buckets per order: at least kSortBuckets, and enough that an average
+  // bucket holds at most half of what the fine pass keeps in registers
+  const int fill = kSortFineRegs * kSortFineBlock / 2;
+  const int target = std::min(kSortBucketsMax, std::max(kSortBuckets, (g.n + fill - 1) / fill));
   for (int o = 0; o < 2; ++o) {
     int sh = 0;
-    while (sh < kSortFineLog && ((sp.nbins[o] + (1 << sh) - 1) >> sh) > kSortBuckets) ++sh;
+    while (sh < kSortFineLog && ((sp.nbins[o] + (1 << sh) - 1) >> sh) > target) ++sh;
     sp.sh[o] = sh;
     sp.nb[o] = (sp.nbins[o] + (1 << sh) - 1) >> sh;
   }

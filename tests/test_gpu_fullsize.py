@@ -8,6 +8,13 @@ the adjoint on the 1M-bead fluid.
   the converged Coulomb force, and the total energy.
 * ions_1m (1M ions, M = 256^3, p = 6, FP32, analytic forces, the bench
   setting): sampled forces against the converged Coulomb force.
+* anisotropic (4M sites in 120 x 120 x 240: +1 chains, -1 counterions,
+  neutral solvent; FP32, ik forces and potentials at every site) at the
+  setting the parameter selector picks for the FP32 bar 5e-4: sampled forces
+  and potentials against the converged Coulomb values.  At this size the
+  counting sort uses more buckets than at one million particles (an average
+  bucket within the fine pass's register path); both sorted orders are
+  checked to be permutations of all sites.
 * Autograd at the 1M-bead geometry: the adjoint's dE/dx and dE/dq against
   central finite differences (h = 1e-4) of the FP64-mode energy on 64 seeded
   particles with no pair within 2h of the cutoff, and the FP32 adjoint
@@ -63,6 +70,27 @@ def test_ions_1m_bench_setting_vs_oracle_samples():
     eps = rms_rel(F[g["sample"]], g["F_conv"])
     print(f"ions_1m fp32 analytic: eps_F={eps:.3e}")
     assert eps <= 1e-4
+
+
+def test_anisotropic_4m_vs_oracle_samples():
+    w = inputs.anisotropic()
+    g = _golden("anisotropic")
+    assert int(g["N"]) == w.N and int(g["seed"]) == w.seed
+    eng = enuf.Enuf(w.box, w.N, 0.7466666666666666, 4.6875, (128, 128, 256), 4, precision="f32",
+                    force_mode="ik")
+    E, F, phi = eng.energy_forces(to_dev(w.x, eng.dtype), to_dev(w.q, eng.dtype), potential=True)
+    torch.cuda.synchronize()
+    s = g["sample"]
+    eps_f = rms_rel(F.double().cpu().numpy()[s], g["F_conv"])
+    eps_p = rms_rel(phi.double().cpu().numpy()[s], g["phi_conv"])
+    print(f"anisotropic 4M fp32: eps_F={eps_f:.3e} eps_phi={eps_p:.3e}")
+    assert eps_f <= 5e-4
+    assert eps_p <= 5e-4
+    counts = eng.stage(enuf.STAGE_COUNTS).cpu().numpy()
+    assert counts[0] == w.N
+    for st in (enuf.STAGE_SORTED, enuf.STAGE_CELLS):
+        perm = np.sort(eng.stage(st).cpu().numpy()[: w.N])
+        assert np.array_equal(perm, np.arange(w.N))
 
 
 def _fd_sample(w, k, h, rng):
