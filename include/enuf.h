@@ -70,7 +70,7 @@ typedef enum {
     ENUF_OPT_GRAPH = 2,       /* 1: replay the launch sequence as a HIP graph; default 0 */
     ENUF_OPT_CHECK = 3,       /* 1: enuf_energy_forces synchronises and reports
                                     ENUF_ENONFINITE itself; default 0 */
-    ENUF_OPT_FORCE_MODE = 4   /* reciprocal forces.  0 (default): ik
+    ENUF_OPT_FORCE_MODE = 4,  /* reciprocal forces.  0 (default): ik
                                  differentiation as in the paper's Eq. 41-42:
                                  three field grids are transformed back and
                                  interpolated; the forces sum to zero up to
@@ -82,6 +82,21 @@ typedef enum {
                                  energy; their sum is zero only to the
                                  method's accuracy.  One inverse transform
                                  instead of three. */
+    ENUF_OPT_SLATER = 5       /* ENUF-DPD (paper Sec. 2.4, Eq. 51-58): value =
+                                 lambda_e > 0, the decay length of Slater-type
+                                 smeared charges (beta = R_c / lambda_e); 0
+                                 (default): point charges.  Each real-space
+                                 pair term is scaled, energy and potential by
+                                 B_U(r) = 1 - (1 + r/lambda_e) exp(-2r/lambda_e)
+                                 and force by B_F(r) = 1 - (1 + 2(r/lambda_e)
+                                 (1 + r/lambda_e)) exp(-2r/lambda_e); the
+                                 reciprocal and self terms are those of point
+                                 charges (the paper's choice of a real-space
+                                 cutoff past which both factors are ~1).  The
+                                 adjoint (enuf_energy_grad) differentiates the
+                                 scaled energy exactly; for the erfc-screened
+                                 pair term that differs from the B_F-scaled
+                                 force, which follows the paper. */
 } enuf_option;
 
 /* Internal buffers enuf_stage_copy() can read (for tests of single steps). */

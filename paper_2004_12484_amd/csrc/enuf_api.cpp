@@ -138,6 +138,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   g.alpha = alpha;
   g.rc = r_c;
   g.ke = 1.0;
+  g.slater = 0.0;
   c->prec = precision;
   c->st = reinterpret_cast<hipStream_t>(stream);
 
@@ -267,6 +268,10 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
     case ENUF_OPT_FORCE_MODE:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "force mode is 0 (ik) or 1 (analytic)");
       ctx->analytic = value == 1.0;
+      return ENUF_OK;
+    case ENUF_OPT_SLATER:
+      if (!(value >= 0.0) || !std::isfinite(value)) return fail(ctx, ENUF_EINVAL, "lambda_e must be >= 0 and finite");
+      ctx->g.slater = value;
       return ENUF_OK;
   }
   return fail(ctx, ENUF_EINVAL, "unknown option");

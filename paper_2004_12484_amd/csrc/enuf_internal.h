@@ -47,6 +47,7 @@ struct Geom {
   double mL[3];
   double cL[3];
   double alpha, rc, ke;
+  double slater;   // ENUF-DPD decay length lambda_e of smeared charges (0: point charges)
 };
 
 // Two-level counting sort layout: particles are counted in `nblk` blocks of

@@ -1980,12 +1980,36 @@ __device__ __forceinline__ unsigned shift_in_lt(unsigned acc, double r2, double 
 }
 
 
+// Correction factors of Slater-type smeared charges (ENUF-DPD, Eq. 57-58)
+// as functions of t = 2 r / lambda_e, given et = exp(-t):
+//   B_F = 1 - e^-t (1 + t + t^2/2)   (the regularised incomplete gamma P(3, t))
+//   B_U = 1 - e^-t (1 + t/2).
+// Below t = 1 both come from their series, e^-t sum_{k>=3} t^k/k! for B_F
+// (to k = 18: truncation below 1e-16 relative) and e^-t (t/2 + t^2/2 + the
+// same sum) for B_U, so they keep their relative accuracy where they vanish
+// (like t^3/6 and t/2) instead of cancelling against 1.
+template <typename R>
+__device__ __forceinline__ void slater_factors(R t, R et, R &bu, R &bf) {
+  if (t < R(1)) {
+    R s = R(1);
+#pragma unroll
+    for (int k = 18; k >= 4; --k) s = fma(s, t * R(1.0 / k), R(1));
+    s *= t * t * t * R(1.0 / 6.0);
+    bf = et * s;
+    bu = et * (R(0.5) * t * (R(1) + t) + s);
+  } else {
+    bf = R(1) - et * (R(1) + t + R(0.5) * t * t);
+    bu = R(1) - et * (R(1) + R(0.5) * t);
+  }
+}
+
 // Constants of the pair sum, formed once on the host (double divisions are
 // costly per thread).  bg times the total charge is the background
 // potential; self times q_i the self potential.
 template <typename R>
 struct PairConst {
   R L[3], iL[3], rc2, al, al2, c2a;
+  R isl;  // 1 / lambda_e of Slater-smeared charges (ENUF-DPD); 0 for point charges
   double bg, self;
 };
 template <typename R>
@@ -2000,6 +2024,7 @@ static PairConst<R> pair_const(const Geom &g) {
   c.al = (R)g.alpha;
   c.al2 = (R)(g.alpha * g.alpha);
   c.c2a = (R)(2.0 * g.alpha / sqpi);
+  c.isl = g.slater > 0.0 ? (R)(1.0 / g.slater) : R(0);
   c.bg = -g.ke * pi / (g.L[0] * g.L[1] * g.L[2] * g.alpha * g.alpha);
   c.self = -2.0 * g.ke * g.alpha / sqpi;
   return c;
@@ -2189,8 +2214,21 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
             const R ir = r2 > R(0) ? rsqrt_r(r2) : R(0);  // r = 0 (itself) marked above, adds nothing
             const R r = r2 * ir;
             const R ex = exp_fast(-al2 * r2);
-            const R ec = erfc_with_exp(al * r, ex) * ir;
-            const R fs = qj * (ec + c2a * ex) * ir * ir;
+            R ec = erfc_with_exp(al * r, ex) * ir;
+            R fs = qj * (ec + c2a * ex) * ir * ir;
+            if (pc.isl > R(0)) {
+              // ENUF-DPD smeared charges (Eq. 57-58), t = 2 r / lambda_e: the
+              // energy and potential scaled by B_U; the force by B_F
+              // (forward), or the exact gradient of B_U erfc(a r)/r
+              // (adjoint), using B_U' = (1 + t) exp(-t) / lambda_e
+              const R t = R(2) * r * pc.isl;
+              const R et = exp_fast(-t);
+              R bu, bf;
+              slater_factors(t, et, bu, bf);
+              if (MODE == 0) fs *= bf;
+              else fs = fs * bu - qj * ec * (pc.isl * (R(1) + t) * et) * ir;
+              ec *= bu;
+            }
             ph += qj * ec;
             fx += fs * ddx;
             fy += fs * ddy;

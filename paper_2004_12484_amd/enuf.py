@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libenuf.so")
 
 ENUF_OK, ENUF_EINVAL, ENUF_ENOMEM, ENUF_EDEVICE, ENUF_ENONFINITE, ENUF_ESTATE, ENUF_EUNSUPPORTED = range(7)
 ENUF_FP64, ENUF_FP32 = 0, 1
-OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE = 0, 1, 2, 3, 4
+OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE, OPT_SLATER = 0, 1, 2, 3, 4, 5
 FORCE_MODES = {"ik": 0, "analytic": 1}
 STAGE_GRID, STAGE_SPECTRUM, STAGE_FIELDS, STAGE_SORTED, STAGE_COUNTS, STAGE_CELLS = range(6)
 PHASES = ("prep", "sort", "spread", "fft_fwd", "influence_z", "fft_inv", "gather", "pair", "finalize")
@@ -90,7 +90,9 @@ class Enuf:
     """
 
     def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False,
-                 force_mode="ik"):
+                 force_mode="ik", slater=None):
+        """slater: decay length lambda_e of ENUF-DPD Slater-type smeared
+        charges (paper Sec. 2.4); None for point charges."""
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("ENUF needs a HIP GPU; torch.cuda.is_available() is False")
@@ -121,6 +123,9 @@ class Enuf:
         self.force_mode = force_mode
         if force_mode != "ik":
             self.set_option(OPT_FORCE_MODE, FORCE_MODES[force_mode])
+        self.slater = slater
+        if slater is not None:
+            self.set_option(OPT_SLATER, float(slater))
         self._E = torch.zeros(5, dtype=torch.float64, device=self.device)
 
     # -- plumbing ---------------------------------------------------------
