@@ -2,10 +2,11 @@
 
     python tests/golden/make_oracle_golden.py [workload ...]
 
-Calls only the direct FP64 Ewald oracle (oracle/ewald.py) on the seeded
-synthetic workloads and writes tests/golden/<workload>_oracle.npz with the
-energy parts and the forces/potentials of a seeded sample of charged
-particles.  The k-space sum runs over every k with exp(-k^2/4 alpha^2) >= tol.
+Calls only the oracle (the direct FP64 Ewald sum, oracle/ewald.py, and the
+ENUF-DPD smeared real-space sum, oracle/dpd.py) on the seeded synthetic
+workloads and writes tests/golden/<workload>_oracle.npz with the energy parts
+and the forces/potentials of a seeded sample of charged particles.  The
+k-space sum runs over every k with exp(-k^2/4 alpha^2) >= tol.
 """
 import os
 import sys
@@ -17,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
+from oracle import dpd  # noqa: E402
 from oracle import ewald  # noqa: E402
 from paper_2004_12484_amd import inputs  # noqa: E402
 
@@ -56,6 +58,29 @@ def make_forces(name):
     print(f"{name}: forces on {len(sample)} sampled ions, oracle {dt:.1f} s -> {path}", flush=True)
 
 
+# ENUF-DPD: the charged fluid as a DPD system (R_c = 1, density ~3,
+# real-space cutoff 3 R_c) of Slater-smeared charges with beta = 1.125: the
+# stored point-charge k-space forces with the smeared real-space sum
+SLATER = {"dpd_slater": ("charged_fluid", 1.0 / 1.125)}
+
+
+def make_slater(name):
+    base, lam = SLATER[name]
+    kw = SPECS[base][0]
+    w = getattr(inputs, base)(**kw)
+    g = np.load(os.path.join(HERE, f"{base}_oracle.npz"))
+    assert int(g["N"]) == w.N and int(g["seed"]) == w.seed and np.isclose(float(g["alpha"]), w.alpha)
+    sample = g["sample"]
+    t = time.time()
+    _, _, p_pt = ewald.real_minimage(w.x, w.q, w.box, w.alpha, w.r_c, w.ke, sample=sample, energy=False)
+    _, f_sl, p_sl = dpd.real_slater(w.x, w.q, w.box, w.alpha, w.r_c, lam, w.ke, sample=sample)
+    dt = time.time() - t
+    path = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(path, sample=sample, F=f_sl + g["F_K"], phi=g["phi"] - p_pt + p_sl,
+                        slater=lam, alpha=w.alpha, r_c=w.r_c, N=w.N, seed=w.seed, tol=g["tol"])
+    print(f"{name}: smeared real space on {len(sample)} sampled beads, oracle {dt:.1f} s -> {path}", flush=True)
+
+
 def make(name):
     kw, ns, tol = SPECS[name]
     w = getattr(inputs, name)(**kw)
@@ -80,5 +105,10 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(SPECS) + list(FORCE_ONLY)):
-        make_forces(n) if n in FORCE_ONLY else make(n)
+    for n in (sys.argv[1:] or list(SPECS) + list(FORCE_ONLY) + list(SLATER)):
+        if n in FORCE_ONLY:
+            make_forces(n)
+        elif n in SLATER:
+            make_slater(n)
+        else:
+            make(n)
