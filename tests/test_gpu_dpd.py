@@ -118,3 +118,25 @@ def test_slater_adjoint_vs_finite_differences():
     err = rms_rel(gx[ok], fd)
     print(f"ENUF-DPD adjoint vs FD: {err:.3e}")
     assert err <= 1e-6
+
+
+def test_slater_option_validation_and_reset():
+    x, q, box = _dpd_system(n=1000, seed=44)
+    alpha, rc, M, p = 0.92, 3.0, (16, 16, 16), 6
+    eng = enuf.Enuf(box, len(q), alpha, rc, M, p, precision="f64")
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(enuf.EnufError) as ei:
+            eng.set_option(enuf.OPT_SLATER, bad)
+        assert ei.value.status == enuf.ENUF_EINVAL
+    xt, qt = to_dev(x, torch.float64), to_dev(q, torch.float64)
+    _, F0, _ = eng.energy_forces(xt, qt)
+    F0 = F0.cpu().numpy()
+    eng.set_option(enuf.OPT_SLATER, LAM)
+    _, F1, _ = eng.energy_forces(xt, qt)
+    F1 = F1.cpu().numpy()
+    # back to point charges: the first result again (up to summation order)
+    eng.set_option(enuf.OPT_SLATER, 0.0)
+    _, F2, _ = eng.energy_forces(xt, qt)
+    F2 = F2.cpu().numpy()
+    assert np.linalg.norm(F1 - F0) > 1e-2 * np.linalg.norm(F0)
+    assert np.linalg.norm(F2 - F0) <= 1e-13 * np.linalg.norm(F0)
