@@ -56,7 +56,7 @@ typedef enum {
     ENUF_EDEVICE = 3,       /* a HIP runtime call failed */
     ENUF_ENONFINITE = 4,    /* non-finite position or charge seen on the device */
     ENUF_ESTATE = 5,        /* call sequence error (e.g. grad before forward) */
-    ENUF_EUNSUPPORTED = 6   /* valid request outside what this build handles */
+    ENUF_EUNSUPPORTED = 6   /* valid request outside what the library handles */
 } enuf_status;
 
 typedef enum { ENUF_FP64 = 0, ENUF_FP32 = 1 } enuf_precision;

@@ -259,7 +259,7 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
     }
     case ENUF_OPT_GRAPH:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "graph is 0 or 1");
-      if (value == 1.0) return fail(ctx, ENUF_EUNSUPPORTED, "graph replay is not available in this build");
+      if (value == 1.0) return fail(ctx, ENUF_EUNSUPPORTED, "graph replay is not available in this library");
       return ENUF_OK;
     case ENUF_OPT_CHECK:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "check is 0 or 1");
