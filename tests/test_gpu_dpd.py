@@ -8,7 +8,8 @@ The system is a DPD fluid (density 3 in units of R_c = 1, beta = 1.125, so
 lambda_e = 0.889, real-space cutoff 3 R_c), half the beads charged: many
 pairs lie closer than lambda_e/2, where the kernel takes the factors'
 series form.
-* FP64 element by element at the mirror tolerances (summation order only).
+* FP64 element by element at the mirror tolerances (summation order only),
+  in both reciprocal force modes.
 * FP32 within the FP32 bar (RMS 5e-5).
 * The adjoint differentiates the scaled energy exactly: dE/dx against
   central differences of the FP64 energy, dE/dq against the potentials.
@@ -66,6 +67,23 @@ def test_slater_fp64_vs_mirror():
     assert np.linalg.norm(phi - ref["phi"]) <= 1e-10 * np.linalg.norm(ref["phi"])
     # the smearing moves the forces far beyond those tolerances
     assert np.linalg.norm(ref["F"] - ref["F_point"]) > 1e-2 * np.linalg.norm(ref["F"])
+
+
+def test_slater_analytic_mode_fp64_vs_mirror():
+    # the smeared real-space sum next to the analytic-derivative reciprocal
+    # forces (minus the mirror's exact gradient of the discrete energy)
+    x, q, box = _dpd_system(seed=45)
+    alpha, rc, M, p = 0.92, 3.0, (32, 32, 32), 6
+    m = em.enuf(x, q, box, alpha, rc, M, p, want_grad=True)
+    e_r, f_r, phi_r = dpd.real_slater(x, q, box, alpha, rc, LAM)
+    eng = enuf.Enuf(box, len(q), alpha, rc, M, p, precision="f64", force_mode="analytic", slater=LAM)
+    E, F, phi = eng.energy_forces(to_dev(x, eng.dtype), to_dev(q, eng.dtype), potential=True)
+    torch.cuda.synchronize()
+    ref_f = -m["grad_K"] + f_r
+    ref_phi = m["phi"] - m["phi_R"] + phi_r
+    assert abs(E.cpu().numpy()[1] - e_r) <= 1e-11 * abs(e_r)
+    assert np.linalg.norm(F.cpu().numpy() - ref_f) <= 1e-10 * np.linalg.norm(ref_f)
+    assert np.linalg.norm(phi.cpu().numpy() - ref_phi) <= 1e-10 * np.linalg.norm(ref_phi)
 
 
 def test_slater_fp32_vs_mirror():
