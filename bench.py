@@ -116,9 +116,10 @@ def measured_traffic(workload, phase):
 
 
 def pair_count(w, nq):
-    """Expected number of (ordered) charged pairs inside r_c for a uniform fluid."""
+    """Expected number of unordered charged pairs inside r_c for a uniform
+    fluid: N_q n_nb / 2 with n_nb = (N_q / V) (4/3) pi r_c^3 neighbours."""
     V = float(np.prod(w.box))
-    return nq * (nq / V) * 4.0 / 3.0 * math.pi * w.r_c ** 3
+    return 0.5 * nq * (nq / V) * 4.0 / 3.0 * math.pi * w.r_c ** 3
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -334,8 +335,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
-    phases = eng.timings()
+    per_step = eng.step_timings(args.steps)          # [K, phases] ms, HIP events on the library's stream
     eng.set_option(enuf.OPT_TIMING, 0)
+    phases = {k: float(v) for k, v in zip(enuf.PHASES, per_step.mean(axis=0))}
+    step_ms = per_step.sum(axis=1)
     ms = ms_total / args.steps
     value = 1000.0 / ms
 
@@ -362,8 +365,12 @@ def main():
         achieved = pairs * PAIR_FLOPS / (phases[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": measured_traffic(w.name, dom),
-                "flops_per_launch": pairs * PAIR_FLOPS}
+                "flops_per_launch": pairs * PAIR_FLOPS, "unordered_pairs": pairs}
     hbm = {k: ab[k] / (phases[k] * 1e-3) / 1e9 for k in ab}
+    # the HBM-bound gates: spread and gather against the HBM peak, with the
+    # counter bytes of their kernels beside them when measured on this build
+    gates = {k: {"algorithmic_bytes": ab[k], "ms": phases[k], "gbs": hbm[k], "frac": hbm[k] / HBM_PEAK_GBS,
+                 "counter_bytes": measured_traffic(w.name, k)} for k in ("spread", "gather")}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -375,7 +382,9 @@ def main():
                    "slater": spec.get("slater"),
                    "seed": w.seed, "parallelism": "single GPU"},
         "ns_per_particle": ms * 1e6 / w.N, "ns_per_charged": ms * 1e6 / max(nq, 1),
-        "wall_s": wall, "phase_ms": phases, "phase_gbs": hbm,
+        "wall_s": wall, "step_ms": {"median": float(np.median(step_ms)), "p10": float(np.percentile(step_ms, 10)),
+                                    "p90": float(np.percentile(step_ms, 90)), "mean": float(step_ms.mean())},
+        "phase_ms": phases, "phase_gbs": hbm, "hbm_gates": gates,
         "energy": {"total": float(Eh[0]), "real": float(Eh[1]), "recip": float(Eh[2]), "self": float(Eh[3]),
                    "background": float(Eh[4])},
         "accuracy": acc, "roofline": roof,

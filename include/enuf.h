@@ -30,8 +30,11 @@
  *    on the context except the text behind enuf_last_error().
  *  - Pointers named "device" must be device memory of the context's GPU
  *    (e.g. a torch tensor's data_ptr()).  The caller owns all of them; the
- *    library never frees caller memory.  The library owns its context and its
- *    internal device workspace, released by enuf_destroy().
+ *    library never frees caller memory.  The library owns its host context.
+ *    Device working memory is the caller's (enuf_workspace_bytes +
+ *    enuf_set_workspace), or allocated by the library only when asked
+ *    (enuf_alloc_workspace, released by enuf_destroy()); enuf_create and the
+ *    evaluation calls allocate no device memory.
  *  - "real" is double for ENUF_FP64 contexts and float for ENUF_FP32.
  *  - Device work is enqueued on the context's HIP stream and is NOT
  *    synchronised on return unless a call says so.  Calls on one context are
@@ -67,7 +70,14 @@ typedef enum {
     ENUF_OPT_TIMING = 1,      /* n > 0: record per-phase HIP events for each
                                     evaluation in a ring of n slots; 0: off
                                     (default) */
-    ENUF_OPT_GRAPH = 2,       /* 1: replay the launch sequence as a HIP graph; default 0 */
+    ENUF_OPT_GRAPH = 2,       /* 1: enuf_energy_forces replays its launch
+                                 sequence as a HIP graph on a stream of the
+                                 context's own, joined to the context stream
+                                 by events before and after (captured on the
+                                 first call and again whenever x, q, E, F,
+                                 phi, the workspace or an option change);
+                                 per-phase timing is not recorded then.
+                                 Default 0 (kernels launched one by one). */
     ENUF_OPT_CHECK = 3,       /* 1: enuf_energy_forces synchronises and reports
                                     ENUF_ENONFINITE itself; default 0 */
     ENUF_OPT_FORCE_MODE = 4,  /* reciprocal forces.  0 (default): ik
@@ -129,14 +139,37 @@ typedef enum {
  *   precision ENUF_FP64 or ENUF_FP32 (spread/FFT/gather/pair arithmetic;
  *            energies are always reduced in double)
  *   stream   hipStream_t to enqueue on (NULL = default stream)
- * Allocates the device workspace (ENUF_ENOMEM on failure).  Selects the
- * current HIP device as the context's device.
+ * Allocates no device memory: give the context a workspace with
+ * enuf_set_workspace() (or enuf_alloc_workspace()) before evaluating.  Selects the current HIP device as the
+ * context's device.
  */
 enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double alpha,
                         double r_c, const int32_t M[3], int32_t p, int32_t precision,
                         void *stream);
 
-/* enuf_destroy -- free the context and its workspace.  NULL -> ENUF_EINVAL. */
+/* enuf_workspace_bytes -- device bytes the context's workspace needs
+ * (particle copies and sort buffers, about 16 reals + 40 bytes per
+ * particle; grid, half spectrum, four field spectra and four field grids,
+ * 10 reals per grid point; tables).  Any alignment of the block is accepted:
+ * the figure includes 256 bytes of slack. */
+enuf_status enuf_workspace_bytes(enuf_ctx ctx, size_t *bytes);
+
+/* enuf_set_workspace -- use caller-owned device memory ws (at least
+ * enuf_workspace_bytes() bytes, e.g. a torch uint8 tensor) as the context's
+ * workspace.  Enqueues its initialisation (FFT twiddles, influence factors,
+ * cleared flags) on the context stream; the memory must stay valid until the
+ * context is destroyed or another workspace is set, and must not be used by
+ * anything else meanwhile.  Forgets the previous evaluation (a following
+ * enuf_energy_grad reports ENUF_ESTATE).  ENUF_EINVAL when ws is NULL or too
+ * small. */
+enuf_status enuf_set_workspace(enuf_ctx ctx, void *ws, size_t bytes);
+
+/* enuf_alloc_workspace -- allocate the workspace with hipMalloc and set it
+ * (owned by the library, freed by enuf_destroy); ENUF_ENOMEM on failure. */
+enuf_status enuf_alloc_workspace(enuf_ctx ctx);
+
+/* enuf_destroy -- free the context and a workspace the library allocated.
+ * NULL -> ENUF_EINVAL. */
 enuf_status enuf_destroy(enuf_ctx ctx);
 
 /* enuf_set_option -- set one enuf_option (value range checked). */
@@ -162,7 +195,7 @@ enuf_status enuf_set_stream(enuf_ctx ctx, void *stream);
  * sum to zero exactly; they approximate -dE/dr.  The exact gradient of the
  * computed energy is available from enuf_energy_grad().  Non-finite input is
  * recorded in a device flag read by enuf_get_flags() (or reported directly
- * with ENUF_OPT_CHECK).
+ * with ENUF_OPT_CHECK).  ENUF_ESTATE when the context has no workspace.
  */
 enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, double *E,
                                void *F, void *phi);
@@ -177,9 +210,23 @@ enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, doubl
  *   dEdx  device real[N*3] out: grad_E * dE/dr_i (window-derivative gather on
  *         the potential grid, plus the real-space gradient), or NULL
  *   dEdq  device real[N] out: grad_E * dE/dq_i, or NULL
+ * The gradient is that of the energy with the parameters (ke, Slater length)
+ * the forward call used, whatever enuf_set_option() changed since.
  * ENUF_ESTATE when no forward evaluation preceded it.
  */
 enuf_status enuf_energy_grad(enuf_ctx ctx, double grad_E, void *dEdx, void *dEdq);
+
+/* enuf_eval_token -- identifier of the context's last enuf_energy_forces()
+ * (a count of evaluations; 0 before the first). */
+enuf_status enuf_eval_token(enuf_ctx ctx, uint64_t *token);
+
+/* enuf_energy_grad_dev -- as enuf_energy_grad(), for the evaluation whose
+ * enuf_eval_token() was `token`, with the upstream gradient read from device
+ * memory grad_E (one double) on the stream, so that no host
+ * synchronisation is needed.  ENUF_ESTATE when the context has evaluated
+ * again since (its kept state belongs to another configuration). */
+enuf_status enuf_energy_grad_dev(enuf_ctx ctx, uint64_t token, const double *grad_E, void *dEdx,
+                                 void *dEdq);
 
 /* enuf_get_flags -- synchronise the stream and return the sticky device
  * flags (bit 0: non-finite input seen); clears them. */
@@ -198,8 +245,15 @@ enuf_status enuf_stage_bytes(enuf_ctx ctx, int32_t stage, size_t *bytes);
  * synchronises, then starts a new averaging window.  Fills up to n values in
  * the order prep, sort, spread, fft_fwd, influence+z, fft_inv, gather, pair,
  * finalize; *count receives the number of phases.  ENUF_ESTATE when timing
- * is off or nothing was recorded. */
+ * is off, nothing was recorded, or graph replay is on. */
 enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count);
+
+/* enuf_get_step_timings -- the same events per evaluation: ms[k * 9 + i] is
+ * phase i of the k-th recorded evaluation (oldest first, at most cap of
+ * them, the last ENUF_OPT_TIMING slots); *count receives the number of
+ * evaluations.  Synchronises and starts a new window, like
+ * enuf_get_timings(). */
+enuf_status enuf_get_step_timings(enuf_ctx ctx, double *ms, int32_t cap, int32_t *count);
 
 /* enuf_status_string -- static text for a status code. */
 const char *enuf_status_string(enuf_status s);

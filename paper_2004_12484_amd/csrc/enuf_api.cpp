@@ -1,10 +1,13 @@
 // enuf_api.cpp -- host side of the ENUF C ABI (include/enuf.h): parameter
-// validation, workspace ownership, stream binding and the launch sequences.
+// validation, the workspace layout, stream binding, HIP graph replay and the
+// launch sequences.  The library allocates no device memory unless asked to
+// (enuf_alloc_workspace).
 #include "enuf.h"
 
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -16,22 +19,49 @@
 using enuf::Geom;
 using enuf::Work;
 
+namespace {
+
+constexpr size_t kAlign = 256;
+
+// The captured launch sequence of one evaluation and the arguments and
+// options it was captured with (a call with other ones captures again).
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const void *x = nullptr, *q = nullptr;
+  double *E = nullptr;
+  void *F = nullptr, *phi = nullptr, *ws = nullptr;
+  bool analytic = false;
+  double ke = 0.0, slater = 0.0;
+};
+
+}  // namespace
+
 struct enuf_ctx_s {
-  Geom g{};
-  Work w{};
+  Geom g{};                    // parameters of the next evaluation
+  Work w{};                    // workspace pointers (valid when have_ws)
+  int nruns = 0;               // spread run-table entries
   int prec = ENUF_FP64;
   hipStream_t st = nullptr;
   int device = 0;
+  bool have_ws = false;
+  void *owned_ws = nullptr;    // workspace from enuf_alloc_workspace
+  // the last evaluation on the context workspace, read by the adjoint
   bool have_forward = false;
   bool last_all_active = false;
+  bool last_analytic = false;  // it left psi as a plain real grid
+  Geom gf{};                   // its parameters (ke, Slater length)
+  uint64_t token = 0;          // evaluations on the context workspace so far
   bool check = false;
   bool analytic = false;       // ENUF_OPT_FORCE_MODE = 1
-  bool last_analytic = false;  // the last forward left psi as a plain real grid
+  // graph replay (ENUF_OPT_GRAPH)
+  bool graph = false;
+  hipStream_t gst = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  GraphCache gc;
   // timing ring: `slots` evaluations x (kPhases + 1) events
   std::vector<hipEvent_t> ring;
   int slots = 0, next = 0, recorded = 0;
   std::string err;
-  std::vector<void *> allocs;
 };
 
 static thread_local std::string g_create_err;
@@ -48,22 +78,139 @@ static enuf_status hip_fail(enuf_ctx c, hipError_t e, const char *what) {
 
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-static void free_all(enuf_ctx c) {
-  for (void *p : c->allocs) (void)hipFree(p);
-  c->allocs.clear();
+static size_t real_bytes(enuf_ctx c) { return c->prec == ENUF_FP64 ? 8 : 4; }
+
+// Workspace layout: every buffer starts on a 256-byte boundary of one block.
+// With base == nullptr only the size is computed.  The size returned includes
+// 256 bytes of slack so that any caller pointer can be aligned up.
+static size_t layout(const Geom &g, size_t rs, char *base, Work *w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    void *p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const size_t n = (size_t)g.n;
+  const size_t G = (size_t)g.M[0] * g.M[1] * g.M[2];
+  const enuf::SortPlan sp = enuf::sort_plan(g, (int)rs);
+  const size_t nbk = (size_t)sp.nb[0] + sp.nb[1];
+  Work t;
+  t.part_t = take(n * 4 * rs);
+  t.part_c = take(n * 4 * rs);
+  t.perm_t = (int *)take(n * 4);
+  t.perm_c = (int *)take(n * 4);
+  t.key_t = (int *)take(n * 4);
+  t.key_c = (int *)take(n * 4);
+  t.off_t = (int *)take(((size_t)sp.nbins[0] + 1) * 4);
+  t.off_c = (int *)take(((size_t)sp.nbins[1] + 1) * 4);
+  t.hist = (int *)take((size_t)sp.nblk * nbk * 4);
+  t.bbase = (int *)take((nbk + 2) * 4);
+  t.stg_t = take(n * 4 * rs);
+  t.stg_c = take(n * 4 * rs);
+  t.ik_t = (int2 *)take(n * sizeof(int2));
+  t.ik_c = (int2 *)take(n * sizeof(int2));
+  t.runs = (int *)take((size_t)5 * enuf::kMaxRuns * 4);
+  t.counts = (int *)take(4 * 4);
+  t.scal = (double *)take(4 * 8);
+  t.qpart = (double *)take((size_t)4 * sp.nblk * 8);
+  t.eslot = (double *)take((size_t)2 * enuf::kESlots * 8);
+  t.grid = take(G * rs);
+  t.spec = take(G / 2 * 2 * rs);
+  t.fspec = take(4 * (G / 2) * 2 * rs);
+  t.field = take(G * 4 * rs);
+  const size_t ntab = enuf::table_size(g, t.tab_off);
+  t.tables = take(ntab * rs);
+  if (w) *w = t;
+  return (off + kAlign - 1) / kAlign * kAlign + kAlign;
+}
+
+static void drop_graph(enuf_ctx c) {
+  if (c->gc.exec) (void)hipGraphExecDestroy(c->gc.exec);
+  c->gc = GraphCache{};
+}
+
+static void release(enuf_ctx c) {
+  drop_graph(c);
+  if (c->owned_ws) (void)hipFree(c->owned_ws);
+  c->owned_ws = nullptr;
   for (auto &e : c->ring) (void)hipEventDestroy(e);
   c->ring.clear();
   c->slots = c->next = c->recorded = 0;
+  for (auto &e : c->gev)
+    if (e) (void)hipEventDestroy(e);
+  c->gev[0] = c->gev[1] = nullptr;
+  if (c->gst) (void)hipStreamDestroy(c->gst);
+  c->gst = nullptr;
 }
 
-template <typename T>
-static hipError_t dalloc(enuf_ctx c, T **p, size_t count) {
-  void *q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T) + 256);
-  if (e != hipSuccess) return e;
-  c->allocs.push_back(q);
-  *p = reinterpret_cast<T *>(q);
-  return hipSuccess;
+static hipError_t sync_stream(enuf_ctx c) { return c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize(); }
+
+// Point the context at a workspace block (aligned up) and enqueue its
+// initialisation on the context stream.
+static enuf_status attach(enuf_ctx c, void *ws) {
+  char *b = (char *)(((uintptr_t)ws + kAlign - 1) & ~(uintptr_t)(kAlign - 1));
+  Work w;
+  layout(c->g, real_bytes(c), b, &w);
+  w.nruns = c->nruns;
+  hipError_t e = enuf::launch_init_ws(c->g, w, c->st, c->prec == ENUF_FP64);
+  if (e != hipSuccess) return hip_fail(c, e, "workspace initialisation");
+  c->w = w;
+  c->have_ws = true;
+  c->have_forward = false;
+  return ENUF_OK;
+}
+
+static hipError_t forward(enuf_ctx c, const Work &w, hipStream_t st, const void *x, const void *q, double *E,
+                          void *F, void *phi, bool all, bool an, hipEvent_t *ev) {
+  if (c->prec == ENUF_FP64)
+    return enuf::launch_forward<double>(c->g, w, st, (const double *)x, (const double *)q, E, (double *)F,
+                                        (double *)phi, all, all, an, ev);
+  return enuf::launch_forward<float>(c->g, w, st, (const float *)x, (const float *)q, E, (float *)F, (float *)phi,
+                                     all, all, an, ev);
+}
+
+// One evaluation replayed as a HIP graph on the context's own stream, joined
+// to the caller's stream by events on both sides.  The graph is captured on
+// the first call and again whenever the pointers or options change.
+static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E, void *F, void *phi, bool all,
+                            bool an) {
+  GraphCache &gc = c->gc;
+  const bool hit = gc.exec && gc.x == x && gc.q == q && gc.E == E && gc.F == F && gc.phi == phi &&
+                   gc.ws == c->w.grid && gc.analytic == an && gc.ke == c->g.ke && gc.slater == c->g.slater;
+  if (!hit) {
+    drop_graph(c);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t el = forward(c, c->w, c->gst, x, q, E, F, phi, all, an, nullptr);
+    e = hipStreamEndCapture(c->gst, &graph);
+    if (el != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return el != hipSuccess ? el : e;
+    }
+    e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gc.exec = nullptr;
+      return e;
+    }
+    gc.x = x;
+    gc.q = q;
+    gc.E = E;
+    gc.F = F;
+    gc.phi = phi;
+    gc.ws = c->w.grid;
+    gc.analytic = an;
+    gc.ke = c->g.ke;
+    gc.slater = c->g.slater;
+  }
+  hipError_t e = hipEventRecord(c->gev[0], c->st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->gst, c->gev[0], 0);
+  if (e == hipSuccess) e = hipGraphLaunch(gc.exec, c->gst);
+  if (e == hipSuccess) e = hipEventRecord(c->gev[1], c->gst);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->gev[1], 0);
+  return e;
 }
 
 extern "C" {
@@ -109,9 +256,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   if (r_c > 0.5 * lmin * (1.0 + 1e-12))
     return fail(nullptr, ENUF_EUNSUPPORTED, "r_c > min(L)/2 (minimum image) is not supported");
 
-  enuf_ctx c = new (std::nothrow) enuf_ctx_s();
-  if (!c) return fail(nullptr, ENUF_ENOMEM, "host allocation failed");
-  Geom &g = c->g;
+  Geom g{};
   const int tdef[3] = {enuf::kTileX, enuf::kTileY, enuf::kTileZ};
   for (int d = 0; d < 3; ++d) {
     g.M[d] = M[d];
@@ -139,93 +284,82 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   g.rc = r_c;
   g.ke = 1.0;
   g.slater = 0.0;
-  c->prec = precision;
-  c->st = reinterpret_cast<hipStream_t>(stream);
 
-  hipError_t e = hipGetDevice(&c->device);
-  if (e != hipSuccess) {
-    enuf_status s = hip_fail(nullptr, e, "hipGetDevice");
-    delete c;
-    return s;
-  }
   const size_t rs = precision == ENUF_FP64 ? 8 : 4;
-  const size_t G = (size_t)M[0] * M[1] * M[2];
-  Work &w = c->w;
-  unsigned char *bytes = nullptr;
-  auto need = [&](hipError_t err) -> bool { return err == hipSuccess; };
-  bool ok = true;
-  ok = ok && need(dalloc(c, (unsigned char **)&w.part_t, (size_t)n * 4 * rs));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.part_c, (size_t)n * 4 * rs));
-  ok = ok && need(dalloc(c, &w.perm_t, (size_t)n));
-  ok = ok && need(dalloc(c, &w.perm_c, (size_t)n));
+  if (!enuf::fft_plans_fit(g, precision == ENUF_FP64))
+    return fail(nullptr, ENUF_EUNSUPPORTED, "grid transform does not fit one workgroup's LDS");
   const enuf::SortPlan sp = enuf::sort_plan(g, (int)rs);
   const size_t nbk = (size_t)sp.nb[0] + sp.nb[1];
-  if (!enuf::fft_plans_fit(g, precision == ENUF_FP64)) {
-    delete c;
-    return fail(nullptr, ENUF_EUNSUPPORTED, "grid transform does not fit one workgroup's LDS");
-  }
-  if (nbk * sizeof(int) > 65536 || enuf::sort_stage_lds(sp, (int)rs) > 65536 || enuf::sort_fine_lds(sp) > 65536) {
-    delete c;
+  if (nbk * sizeof(int) > 65536 || enuf::sort_stage_lds(sp, (int)rs) > 65536 || enuf::sort_fine_lds(sp) > 65536)
     return fail(nullptr, ENUF_EUNSUPPORTED, "too many sort buckets for one workgroup's LDS");
-  }
-  ok = ok && need(dalloc(c, &w.key_t, (size_t)n));
-  ok = ok && need(dalloc(c, &w.key_c, (size_t)n));
-  ok = ok && need(dalloc(c, &w.off_t, (size_t)sp.nbins[0] + 1));
-  ok = ok && need(dalloc(c, &w.off_c, (size_t)sp.nbins[1] + 1));
-  ok = ok && need(dalloc(c, &w.hist, (size_t)sp.nblk * nbk));
-  ok = ok && need(dalloc(c, &w.bbase, nbk + 2));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.stg_t, (size_t)n * 4 * rs));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.stg_c, (size_t)n * 4 * rs));
-  ok = ok && need(dalloc(c, &w.ik_t, (size_t)n));
-  ok = ok && need(dalloc(c, &w.ik_c, (size_t)n));
-  ok = ok && need(dalloc(c, &w.runs, (size_t)5 * enuf::kMaxRuns));
-  ok = ok && need(dalloc(c, &w.counts, 4));
-  ok = ok && need(dalloc(c, &w.scal, 4));
-  ok = ok && need(dalloc(c, &w.qpart, (size_t)4 * sp.nblk));
-  ok = ok && need(dalloc(c, &w.eslot, (size_t)2 * enuf::kESlots));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.grid, G * rs));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.spec, G / 2 * 2 * rs));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.fspec, 4 * (G / 2) * 2 * rs));
-  ok = ok && need(dalloc(c, (unsigned char **)&w.field, G * 4 * rs));
-  size_t ntab = enuf::table_size(g, w.tab_off);
-  ok = ok && need(dalloc(c, (unsigned char **)&w.tables, ntab * rs));
-  (void)bytes;
-  if (!ok || std::getenv("ENUF_FAIL_ALLOC")) {
-    free_all(c);
-    delete c;
-    return fail(nullptr, ENUF_ENOMEM, "device workspace allocation failed");
-  }
-  // tables
-  std::vector<unsigned char> host(ntab * rs);
-  if (precision == ENUF_FP64) enuf::fill_tables<double>(g, w.tab_off, (double *)host.data());
-  else enuf::fill_tables<float>(g, w.tab_off, (float *)host.data());
   int runs[5 * enuf::kMaxRuns];
-  w.nruns = enuf::build_runs(g, runs);
-  if (w.nruns <= 0) {
-    free_all(c);
-    delete c;
-    return fail(nullptr, ENUF_EUNSUPPORTED, "spread run table overflow");
+  const int nruns = enuf::build_runs(g, runs);
+  if (nruns <= 0) return fail(nullptr, ENUF_EUNSUPPORTED, "spread run table overflow");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+
+  enuf_ctx c = new (std::nothrow) enuf_ctx_s();
+  if (!c) return fail(nullptr, ENUF_ENOMEM, "host allocation failed");
+  c->g = g;
+  c->nruns = nruns;
+  c->prec = precision;
+  c->st = reinterpret_cast<hipStream_t>(stream);
+  c->device = dev;
+  *out = c;
+  return ENUF_OK;
+}
+
+enuf_status enuf_workspace_bytes(enuf_ctx ctx, size_t *bytes) {
+  if (!ctx || !bytes) return fail(ctx, ENUF_EINVAL, "ctx or bytes is NULL");
+  *bytes = layout(ctx->g, real_bytes(ctx), nullptr, nullptr);
+  return ENUF_OK;
+}
+
+enuf_status enuf_set_workspace(enuf_ctx ctx, void *ws, size_t bytes) {
+  if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
+  if (!ws) return fail(ctx, ENUF_EINVAL, "workspace pointer is NULL");
+  const size_t need = layout(ctx->g, real_bytes(ctx), nullptr, nullptr);
+  if (bytes < need)
+    return fail(ctx, ENUF_EINVAL, "workspace too small: " + std::to_string(bytes) + " bytes given, " +
+                                      std::to_string(need) + " needed (enuf_workspace_bytes)");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  if (ctx->owned_ws) {
+    // the library's own block may still be in use by enqueued work
+    e = sync_stream(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "synchronize");
+    (void)hipFree(ctx->owned_ws);
+    ctx->owned_ws = nullptr;
   }
-  e = hipMemcpy(w.tables, host.data(), ntab * rs, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(w.runs, runs, sizeof(int) * 5 * w.nruns, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(w.counts, 0, 4 * sizeof(int));
-  if (e == hipSuccess) e = hipMemset(w.eslot, 0, 2 * enuf::kESlots * sizeof(double));
-  if (e != hipSuccess) {
-    enuf_status s = hip_fail(nullptr, e, "workspace initialisation");
-    free_all(c);
-    delete c;
+  drop_graph(ctx);
+  ctx->have_ws = false;
+  return attach(ctx, ws);
+}
+
+enuf_status enuf_alloc_workspace(enuf_ctx ctx) {
+  if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
+  const size_t need = layout(ctx->g, real_bytes(ctx), nullptr, nullptr);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  void *p = nullptr;
+  if (std::getenv("ENUF_FAIL_ALLOC") || hipMalloc(&p, need) != hipSuccess)
+    return fail(ctx, ENUF_ENOMEM, "device workspace allocation of " + std::to_string(need) + " bytes failed");
+  enuf_status s = enuf_set_workspace(ctx, p, need);
+  if (s != ENUF_OK) {
+    (void)hipFree(p);
     return s;
   }
-  *out = c;
+  ctx->owned_ws = p;
   return ENUF_OK;
 }
 
 enuf_status enuf_destroy(enuf_ctx ctx) {
   if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
   (void)hipSetDevice(ctx->device);
-  if (ctx->st) (void)hipStreamSynchronize(ctx->st);
-  else (void)hipDeviceSynchronize();
-  free_all(ctx);
+  (void)sync_stream(ctx);
+  if (ctx->gst) (void)hipStreamSynchronize(ctx->gst);
+  release(ctx);
   delete ctx;
   return ENUF_OK;
 }
@@ -257,10 +391,21 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       }
       return ENUF_OK;
     }
-    case ENUF_OPT_GRAPH:
+    case ENUF_OPT_GRAPH: {
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "graph is 0 or 1");
-      if (value == 1.0) return fail(ctx, ENUF_EUNSUPPORTED, "graph replay is not available in this library");
+      drop_graph(ctx);
+      ctx->graph = value == 1.0;
+      if (ctx->graph && !ctx->gst) {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->gst, hipStreamNonBlocking);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ctx->gev[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+          ctx->graph = false;
+          return hip_fail(ctx, e, "graph stream set-up");
+        }
+      }
       return ENUF_OK;
+    }
     case ENUF_OPT_CHECK:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "check is 0 or 1");
       ctx->check = value == 1.0;
@@ -283,15 +428,16 @@ enuf_status enuf_set_stream(enuf_ctx ctx, void *stream) {
   return ENUF_OK;
 }
 
-static enuf_status read_flags(enuf_ctx ctx, int32_t *flags, bool clear) {
-  hipError_t e = ctx->st ? hipStreamSynchronize(ctx->st) : hipDeviceSynchronize();
+static enuf_status read_flags_at(enuf_ctx ctx, int *counts, int32_t *flags, bool clear) {
+  hipError_t e = sync_stream(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "synchronize");
   int h[4];
-  e = hipMemcpy(h, ctx->w.counts, sizeof(h), hipMemcpyDeviceToHost);
+  e = hipMemcpy(h, counts, sizeof(h), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "flag read");
   *flags = h[2];
   if (clear && h[2]) {
-    e = hipMemset(ctx->w.counts + 2, 0, sizeof(int));
+    const int zero = 0;
+    e = hipMemcpy(counts + 2, &zero, sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "flag clear");
   }
   return ENUF_OK;
@@ -300,61 +446,83 @@ static enuf_status read_flags(enuf_ctx ctx, int32_t *flags, bool clear) {
 enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, double *E, void *F, void *phi) {
   if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
   if (!x || !q || !E) return fail(ctx, ENUF_EINVAL, "x, q and E must not be NULL");
+  if (!ctx->have_ws)
+    return fail(ctx, ENUF_ESTATE, "no workspace: call enuf_set_workspace or enuf_alloc_workspace first");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   const bool all = phi != nullptr;
-  hipEvent_t *ev = nullptr;
-  if (ctx->slots > 0) {
-    ev = &ctx->ring[(size_t)ctx->next * (enuf::kPhases + 1)];
-    ctx->next = (ctx->next + 1) % ctx->slots;
-    ctx->recorded = std::min(ctx->recorded + 1, ctx->slots);
-  }
   const bool an = ctx->analytic;
-  if (ctx->prec == ENUF_FP64)
-    e = enuf::launch_forward<double>(ctx->g, ctx->w, ctx->st, (const double *)x, (const double *)q, E,
-                                     (double *)F, (double *)phi, all, all, an, ev);
-  else
-    e = enuf::launch_forward<float>(ctx->g, ctx->w, ctx->st, (const float *)x, (const float *)q, E,
-                                    (float *)F, (float *)phi, all, all, an, ev);
+  if (ctx->graph) {
+    e = run_graph(ctx, x, q, E, F, phi, all, an);
+  } else {
+    hipEvent_t *ev = nullptr;
+    if (ctx->slots > 0) {
+      ev = &ctx->ring[(size_t)ctx->next * (enuf::kPhases + 1)];
+      ctx->next = (ctx->next + 1) % ctx->slots;
+      ctx->recorded = std::min(ctx->recorded + 1, ctx->slots);
+    }
+    e = forward(ctx, ctx->w, ctx->st, x, q, E, F, phi, all, an, ev);
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->have_forward = true;
   ctx->last_all_active = all;
   ctx->last_analytic = an;
+  ctx->gf = ctx->g;
+  ++ctx->token;
   if (ctx->check) {
     int32_t f = 0;
-    enuf_status s = read_flags(ctx, &f, true);
+    enuf_status s = read_flags_at(ctx, ctx->w.counts, &f, true);
     if (s != ENUF_OK) return s;
     if (f & 1) return fail(ctx, ENUF_ENONFINITE, "non-finite position or charge (excluded from the sums)");
   }
   return ENUF_OK;
 }
 
-enuf_status enuf_energy_grad(enuf_ctx ctx, double grad_E, void *dEdx, void *dEdq) {
-  if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
-  if (!std::isfinite(grad_E)) return fail(ctx, ENUF_EINVAL, "grad_E must be finite");
+static enuf_status adjoint(enuf_ctx ctx, double grad_E, const double *gdev, void *dEdx, void *dEdq) {
   if (!ctx->have_forward) return fail(ctx, ENUF_ESTATE, "no forward evaluation on this context");
   if (!ctx->last_all_active)
     return fail(ctx, ENUF_ESTATE, "the adjoint needs the forward call made with phi != NULL");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (ctx->prec == ENUF_FP64)
-    e = enuf::launch_adjoint<double>(ctx->g, ctx->w, ctx->st, grad_E, (double *)dEdx, (double *)dEdq,
-                                     ctx->last_analytic);
+    e = enuf::launch_adjoint<double>(ctx->gf, ctx->w, ctx->st, grad_E, (double *)dEdx, (double *)dEdq,
+                                     ctx->last_analytic, gdev);
   else
-    e = enuf::launch_adjoint<float>(ctx->g, ctx->w, ctx->st, grad_E, (float *)dEdx, (float *)dEdq,
-                                    ctx->last_analytic);
+    e = enuf::launch_adjoint<float>(ctx->gf, ctx->w, ctx->st, grad_E, (float *)dEdx, (float *)dEdq,
+                                    ctx->last_analytic, gdev);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   return ENUF_OK;
 }
 
+enuf_status enuf_energy_grad(enuf_ctx ctx, double grad_E, void *dEdx, void *dEdq) {
+  if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
+  if (!std::isfinite(grad_E)) return fail(ctx, ENUF_EINVAL, "grad_E must be finite");
+  return adjoint(ctx, grad_E, nullptr, dEdx, dEdq);
+}
+
+enuf_status enuf_eval_token(enuf_ctx ctx, uint64_t *token) {
+  if (!ctx || !token) return fail(ctx, ENUF_EINVAL, "ctx or token is NULL");
+  *token = ctx->token;
+  return ENUF_OK;
+}
+
+enuf_status enuf_energy_grad_dev(enuf_ctx ctx, uint64_t token, const double *grad_E, void *dEdx, void *dEdq) {
+  if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
+  if (!grad_E) return fail(ctx, ENUF_EINVAL, "grad_E is NULL");
+  if (!ctx->have_forward || token != ctx->token)
+    return fail(ctx, ENUF_ESTATE, "the evaluation this gradient belongs to is no longer the context's last one");
+  return adjoint(ctx, 1.0, grad_E, dEdx, dEdq);
+}
+
 enuf_status enuf_get_flags(enuf_ctx ctx, int32_t *flags) {
   if (!ctx || !flags) return fail(ctx, ENUF_EINVAL, "ctx or flags is NULL");
-  return read_flags(ctx, flags, true);
+  if (!ctx->have_ws) return fail(ctx, ENUF_ESTATE, "no workspace");
+  return read_flags_at(ctx, ctx->w.counts, flags, true);
 }
 
 enuf_status enuf_stage_bytes(enuf_ctx ctx, int32_t stage, size_t *bytes) {
   if (!ctx || !bytes) return fail(ctx, ENUF_EINVAL, "ctx or bytes is NULL");
-  const size_t rs = ctx->prec == ENUF_FP64 ? 8 : 4;
+  const size_t rs = real_bytes(ctx);
   const size_t G = (size_t)ctx->g.M[0] * ctx->g.M[1] * ctx->g.M[2];
   switch (stage) {
     case ENUF_STAGE_GRID: *bytes = G * rs; return ENUF_OK;
@@ -383,7 +551,7 @@ enuf_status enuf_stage_copy(enuf_ctx ctx, int32_t stage, void *dst, size_t bytes
     case ENUF_STAGE_COUNTS: src = ctx->w.counts; break;
     case ENUF_STAGE_CELLS: src = ctx->w.perm_c; break;
   }
-  hipError_t e = ctx->st ? hipStreamSynchronize(ctx->st) : hipDeviceSynchronize();
+  hipError_t e = sync_stream(ctx);
   if (e == hipSuccess) e = hipMemcpy(dst, src, need, hipMemcpyDeviceToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "stage copy");
   return ENUF_OK;
@@ -391,8 +559,9 @@ enuf_status enuf_stage_copy(enuf_ctx ctx, int32_t stage, void *dst, size_t bytes
 
 enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count) {
   if (!ctx || !ms || !count) return fail(ctx, ENUF_EINVAL, "NULL argument");
+  if (ctx->graph) return fail(ctx, ENUF_ESTATE, "per-phase timing is not recorded in graph mode");
   if (ctx->slots == 0 || ctx->recorded == 0) return fail(ctx, ENUF_ESTATE, "timing is off or nothing ran");
-  hipError_t e = ctx->st ? hipStreamSynchronize(ctx->st) : hipDeviceSynchronize();
+  hipError_t e = sync_stream(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "synchronize");
   double acc[enuf::kPhases] = {0};
   for (int k = 0; k < ctx->recorded; ++k) {
@@ -407,6 +576,29 @@ enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count
   }
   *count = enuf::kPhases;
   for (int i = 0; i < enuf::kPhases && i < n; ++i) ms[i] = acc[i] / ctx->recorded;
+  ctx->recorded = 0;
+  return ENUF_OK;
+}
+
+enuf_status enuf_get_step_timings(enuf_ctx ctx, double *ms, int32_t cap, int32_t *count) {
+  if (!ctx || !ms || !count) return fail(ctx, ENUF_EINVAL, "NULL argument");
+  if (ctx->graph) return fail(ctx, ENUF_ESTATE, "per-phase timing is not recorded in graph mode");
+  if (ctx->slots == 0 || ctx->recorded == 0) return fail(ctx, ENUF_ESTATE, "timing is off or nothing ran");
+  hipError_t e = sync_stream(ctx);
+  if (e != hipSuccess) return hip_fail(ctx, e, "synchronize");
+  const int nrec = std::min(ctx->recorded, (int)std::max(0, cap));
+  // oldest first
+  for (int k = 0; k < nrec; ++k) {
+    const int slot = (ctx->next - ctx->recorded + k + 2 * ctx->slots) % ctx->slots;
+    hipEvent_t *ev = &ctx->ring[(size_t)slot * (enuf::kPhases + 1)];
+    for (int i = 0; i < enuf::kPhases; ++i) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+      ms[(size_t)k * enuf::kPhases + i] = t;
+    }
+  }
+  *count = nrec;
   ctx->recorded = 0;
   return ENUF_OK;
 }

@@ -98,14 +98,15 @@ struct Work {
 
 // Runs of (neighbour tile offset, class range) a spread tile reads; returns
 // the number of runs and writes 5 ints per run into out (kMaxRuns capacity).
-int build_runs(const Geom &g, int *out);
+__host__ __device__ int build_runs(const Geom &g, int *out);
 // Every transform pass of the grid fits one workgroup's LDS.
 bool fft_plans_fit(const Geom &g, bool fp64);
 
-// Fill the twiddle / window tables on the host (size in reals returned by
-// table_size()).  `host` must hold table_size(g) reals of the precision.
+// Twiddle / window tables: offsets (in reals) of each table, total size returned.
 size_t table_size(const Geom &g, size_t off[kTabSlots]);
-template <typename R> void fill_tables(const Geom &g, const size_t off[kTabSlots], R *host);
+// Enqueue the workspace initialisation on `st`: tables, spread run table,
+// cleared flags and energy slots (kernels only, no host copy).
+hipError_t launch_init_ws(const Geom &g, const Work &w, hipStream_t st, bool fp64);
 
 // One forward evaluation: every phase enqueued on `st`.  `ev` (optional) is
 // an array of kPhases+1 events recorded between phases.  analytic: forces
@@ -118,9 +119,10 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
                           hipEvent_t *ev);
 
 // Adjoint of the last forward: dEdx, dEdq (either may be null).  psi_scalar:
-// the last forward left psi as a plain real grid (analytic mode).
+// the last forward left psi as a plain real grid (analytic mode).  gdev
+// (optional): device double multiplying both outputs after gscale.
 template <typename R>
 hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double gscale, R *dEdx,
-                          R *dEdq, bool psi_scalar);
+                          R *dEdq, bool psi_scalar, const double *gdev);
 
 }  // namespace enuf

@@ -2342,7 +2342,7 @@ SortPlan sort_plan(const Geom &g, int real_bytes) {
   return sp;
 }
 
-int build_runs(const Geom &g, int *out) {
+__host__ __device__ int build_runs(const Geom &g, int *out) {
   int n = 0;
   int offs[3][3], no[3];
   for (int d = 0; d < 3; ++d) {
@@ -2476,40 +2476,79 @@ size_t table_size(const Geom &g, size_t off[kTabSlots]) {
   return o;
 }
 
+// Workspace initialisation, on the device so that a workspace can be set up
+// by kernels alone (no host copy): every table entry in FP64, cast to the
+// precision.  Twiddles e^{-2 pi i m / period}; per axis the influence factor
+// s_d = exp(-k_d^2 / 4 alpha^2) / c_d^2 with the window transform
+// c_d = sinc^p(pi n / M_d) (n signed; zero at the Nyquist index, which is
+// outside the k-set) and the wave number k_d = 2 pi n / L_d.  Thread 0 also
+// writes the spread run table and clears the flags; block 0 clears the
+// energy slots.
+struct TabOff {
+  size_t o[kTabSlots];
+};
 template <typename R>
-void fill_tables(const Geom &g, const size_t off[kTabSlots], R *h) {
+__global__ __launch_bounds__(256) void k_init_ws(Geom g, TabOff t, R *__restrict__ tab, int *__restrict__ runs,
+                                                 int *__restrict__ counts, double *__restrict__ eslot) {
   const double pi = 3.14159265358979323846;
-  auto tw = [&](R *dst, int n, int period) {
-    for (int m = 0; m < n; ++m) {
-      const double a = -2.0 * pi * (double)m / (double)period;
-      dst[2 * m] = (R)std::cos(a);
-      dst[2 * m + 1] = (R)std::sin(a);
-    }
-  };
-  tw(h + off[0], g.M[0] / 2, g.M[0] / 2);
-  tw(h + off[1], g.M[0] / 2, g.M[0]);
-  tw(h + off[2], g.M[1], g.M[1]);
-  tw(h + off[3], g.M[2], g.M[2]);
-  // per axis: s_d = exp(-k_d^2 / 4 alpha^2) / c_d^2 with the window transform
-  // c_d = sinc^p(pi n / M_d) (n signed; zero at the Nyquist index, which is
-  // outside the k-set), and k_d = 2 pi n / L_d
-  auto axis = [&](R *s, R *kv, int cnt, int d) {
-    const int M = g.M[d];
-    for (int k = 0; k < cnt; ++k) {
+  const size_t total = t.o[kTabSlots - 1];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    int seg = 0;
+    while (seg < kTabSlots - 2 && i >= t.o[seg + 1]) ++seg;
+    const int k = (int)(i - t.o[seg]);
+    double v;
+    if (seg < 4) {
+      const int period = seg == 0 ? g.M[0] / 2 : seg == 1 ? g.M[0] : seg == 2 ? g.M[1] : g.M[2];
+      double sn, cs;
+      sincospi(-2.0 * (double)(k >> 1) / (double)period, &sn, &cs);
+      v = (k & 1) ? sn : cs;
+    } else {
+      const int d = seg < 7 ? seg - 4 : seg - 7;
+      const int M = g.M[d];
       const int nn = k < M / 2 ? k : k - M;
-      const double t = pi * (double)nn / (double)M;
-      const double c = std::pow(nn == 0 ? 1.0 : std::sin(t) / t, g.p);
       const double kd = 2.0 * pi * (double)nn / g.L[d];
-      s[k] = (k == M / 2) ? R(0) : (R)(std::exp(-kd * kd / (4.0 * g.alpha * g.alpha)) / (c * c));
-      kv[k] = (R)kd;
+      if (seg >= 7) {
+        v = kd;
+      } else if (k == M / 2) {
+        v = 0.0;
+      } else {
+        const double r = nn == 0 ? 1.0 : sinpi((double)nn / (double)M) / (pi * (double)nn / (double)M);
+        double c = 1.0;
+        for (int j = 0; j < g.p; ++j) c *= r;
+        v = exp(-kd * kd / (4.0 * g.alpha * g.alpha)) / (c * c);
+      }
     }
-  };
-  axis(h + off[4], h + off[7], g.M[0] / 2, 0);
-  axis(h + off[5], h + off[8], g.M[1], 1);
-  axis(h + off[6], h + off[9], g.M[2], 2);
+    tab[i] = (R)v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    build_runs(g, runs);
+    for (int j = 0; j < 4; ++j) counts[j] = 0;
+  }
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < 2 * kESlots; j += blockDim.x) eslot[j] = 0.0;
 }
-template void fill_tables<float>(const Geom &, const size_t[kTabSlots], float *);
-template void fill_tables<double>(const Geom &, const size_t[kTabSlots], double *);
+
+hipError_t launch_init_ws(const Geom &g, const Work &w, hipStream_t st, bool fp64) {
+  TabOff t;
+  for (int i = 0; i < kTabSlots; ++i) t.o[i] = w.tab_off[i];
+  const int nb = (int)std::min<size_t>(64, (t.o[kTabSlots - 1] + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL((k_init_ws<double>), dim3(nb), dim3(256), 0, st, g, t, (double *)w.tables, w.runs, w.counts,
+                       w.eslot);
+  else
+    hipLaunchKernelGGL((k_init_ws<float>), dim3(nb), dim3(256), 0, st, g, t, (float *)w.tables, w.runs, w.counts,
+                       w.eslot);
+  return hipGetLastError();
+}
+
+// Multiply a device array by a device scalar (the adjoint's upstream
+// gradient when it lives in device memory).
+template <typename R>
+__global__ void k_scale_dev(R *__restrict__ a, long long n, const double *__restrict__ s) {
+  const R f = (R)*s;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a[i] *= f;
+}
 
 #define ENUF_TRY(x)                   \
   do {                                \
@@ -2694,7 +2733,7 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
 
 template <typename R>
 hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double gscale, R *dEdx, R *dEdq,
-                          bool psi_scalar) {
+                          bool psi_scalar, const double *gdev) {
   if (dEdx) hipLaunchKernelGGL((k_fill_real<R>), dim3(256), dim3(kBlock), 0, st, dEdx, 3LL * g.n);
   if (dEdq) hipLaunchKernelGGL((k_fill_real<R>), dim3(256), dim3(kBlock), 0, st, dEdq, (long long)g.n);
   ENUF_TRY(hipGetLastError());
@@ -2709,6 +2748,11 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
   else
     hipLaunchKernelGGL((k_pair<R, 1, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
                        w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.eslot);
+  ENUF_TRY(hipGetLastError());
+  if (gdev) {
+    if (dEdx) hipLaunchKernelGGL((k_scale_dev<R>), dim3(256), dim3(kBlock), 0, st, dEdx, 3LL * g.n, gdev);
+    if (dEdq) hipLaunchKernelGGL((k_scale_dev<R>), dim3(256), dim3(kBlock), 0, st, dEdq, (long long)g.n, gdev);
+  }
   return hipGetLastError();
 }
 
@@ -2717,8 +2761,9 @@ template hipError_t launch_forward<float>(const Geom &, const Work &, hipStream_
 template hipError_t launch_forward<double>(const Geom &, const Work &, hipStream_t, const double *,
                                            const double *, double *, double *, double *, bool, bool, bool,
                                            hipEvent_t *);
-template hipError_t launch_adjoint<float>(const Geom &, const Work &, hipStream_t, double, float *, float *, bool);
+template hipError_t launch_adjoint<float>(const Geom &, const Work &, hipStream_t, double, float *, float *, bool,
+                                          const double *);
 template hipError_t launch_adjoint<double>(const Geom &, const Work &, hipStream_t, double, double *, double *,
-                                           bool);
+                                           bool, const double *);
 
 }  // namespace enuf

@@ -25,9 +25,11 @@ PHASES = ("prep", "sort", "spread", "fft_fwd", "influence_z", "fft_inv", "gather
 
 # every symbol include/enuf.h declares
 EXPORTS = (
-    "enuf_create", "enuf_destroy", "enuf_set_option", "enuf_set_stream", "enuf_energy_forces",
-    "enuf_energy_grad", "enuf_get_flags", "enuf_stage_copy", "enuf_stage_bytes", "enuf_get_timings",
-    "enuf_status_string", "enuf_last_error", "enuf_device_count",
+    "enuf_create", "enuf_workspace_bytes", "enuf_set_workspace", "enuf_alloc_workspace", "enuf_destroy",
+    "enuf_set_option", "enuf_set_stream", "enuf_energy_forces",
+    "enuf_energy_grad", "enuf_eval_token", "enuf_energy_grad_dev", "enuf_get_flags", "enuf_stage_copy",
+    "enuf_stage_bytes", "enuf_get_timings", "enuf_get_step_timings", "enuf_status_string", "enuf_last_error",
+    "enuf_device_count",
 )
 
 _lib = None
@@ -50,11 +52,17 @@ def load_library():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, d, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     lib.enuf_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(d), i64, d, d, ctypes.POINTER(i32), i32, i32, vp]
+    lib.enuf_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.enuf_set_workspace.argtypes = [vp, vp, sz]
+    lib.enuf_alloc_workspace.argtypes = [vp]
     lib.enuf_destroy.argtypes = [vp]
     lib.enuf_set_option.argtypes = [vp, i32, d]
     lib.enuf_set_stream.argtypes = [vp, vp]
     lib.enuf_energy_forces.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.enuf_energy_grad.argtypes = [vp, d, vp, vp]
+    lib.enuf_eval_token.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.enuf_energy_grad_dev.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
+    lib.enuf_get_step_timings.argtypes = [vp, ctypes.POINTER(d), i32, ctypes.POINTER(i32)]
     lib.enuf_get_flags.argtypes = [vp, ctypes.POINTER(i32)]
     lib.enuf_stage_copy.argtypes = [vp, i32, vp, sz]
     lib.enuf_stage_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
@@ -90,9 +98,10 @@ class Enuf:
     """
 
     def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False,
-                 force_mode="ik", slater=None):
+                 force_mode="ik", slater=None, workspace=True):
         """slater: decay length lambda_e of ENUF-DPD Slater-type smeared
-        charges (paper Sec. 2.4); None for point charges."""
+        charges (paper Sec. 2.4); None for point charges.  workspace: give
+        the context a workspace held in a torch uint8 tensor (False: none)."""
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("ENUF needs a HIP GPU; torch.cuda.is_available() is False")
@@ -116,6 +125,15 @@ class Enuf:
             if st != ENUF_OK:
                 msg = lib.enuf_last_error(None).decode(errors="replace")
                 raise EnufError(st, msg)
+        self._ws = None
+        if workspace:
+            nb = ctypes.c_size_t()
+            _check(lib.enuf_workspace_bytes(self._h, ctypes.byref(nb)), self._h)
+            with torch.cuda.device(self.device):
+                self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+                self._bind_stream()
+                _check(lib.enuf_set_workspace(self._h, _ptr(self._ws), nb.value), self._h)
+        self._ke = float(ke)
         if ke != 1.0:
             self.set_option(OPT_KE, ke)
         if check:
@@ -131,6 +149,25 @@ class Enuf:
     # -- plumbing ---------------------------------------------------------
     def set_option(self, opt, value):
         _check(load_library().enuf_set_option(self._h, int(opt), float(value)), self._h)
+        if opt == OPT_KE:
+            self._ke = float(value)
+        elif opt == OPT_SLATER:
+            self.slater = float(value) if value > 0 else None
+        elif opt == OPT_FORCE_MODE:
+            self.force_mode = "analytic" if value == 1 else "ik"
+
+    def options(self):
+        """The options an evaluation depends on: (ke, Slater length, force mode)."""
+        return (self._ke, self.slater, self.force_mode)
+
+    def set_options(self, opts):
+        ke, slater, mode = opts
+        if ke != self._ke:
+            self.set_option(OPT_KE, ke)
+        if slater != self.slater:
+            self.set_option(OPT_SLATER, 0.0 if slater is None else slater)
+        if mode != self.force_mode:
+            self.set_option(OPT_FORCE_MODE, FORCE_MODES[mode])
 
     def _bind_stream(self):
         stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -147,6 +184,7 @@ class Enuf:
         if getattr(self, "_h", None) and self._h.value:
             load_library().enuf_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._ws = None
 
     def __del__(self):
         try:
@@ -169,12 +207,31 @@ class Enuf:
         self._keep = (x, q)
         return E, F, phi
 
+    def token(self):
+        """Identifier of the last evaluation on this context."""
+        t = ctypes.c_uint64()
+        _check(load_library().enuf_eval_token(self._h, ctypes.byref(t)), self._h)
+        return int(t.value)
+
     def energy_grad(self, grad_E=1.0, dx=True, dq=True):
         """Exact gradient of the last evaluated energy, scaled by grad_E."""
         self._bind_stream()
         gx = torch.empty((self.n, 3), dtype=self.dtype, device=self.device) if dx else None
         gq = torch.empty(self.n, dtype=self.dtype, device=self.device) if dq else None
         _check(load_library().enuf_energy_grad(self._h, float(grad_E), _ptr(gx), _ptr(gq)), self._h)
+        return gx, gq
+
+    def energy_grad_dev(self, token, grad_E, dx=True, dq=True):
+        """Exact gradient of the evaluation `token`, scaled by the device
+        float64 scalar grad_E (no host synchronisation).  Raises EnufError
+        with status ENUF_ESTATE if the context has evaluated since."""
+        self._bind_stream()
+        g = grad_E.detach().to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
+        gx = torch.empty((self.n, 3), dtype=self.dtype, device=self.device) if dx else None
+        gq = torch.empty(self.n, dtype=self.dtype, device=self.device) if dq else None
+        _check(load_library().enuf_energy_grad_dev(self._h, ctypes.c_uint64(token), _ptr(g), _ptr(gx), _ptr(gq)),
+               self._h)
+        self._keep_grad = g
         return gx, gq
 
     def flags(self):
@@ -196,6 +253,8 @@ class Enuf:
         if which == STAGE_SPECTRUM:
             return buf.view(self.dtype).view(Mz, My, Mx // 2, 2)
         if which == STAGE_FIELDS:
+            if nb.value == G * buf.view(self.dtype).element_size():
+                return buf.view(self.dtype).view(Mz, My, Mx)  # analytic mode: psi alone
             return buf.view(self.dtype).view(Mz, My, Mx, 4)
         return buf.view(torch.int32)
 
@@ -206,21 +265,51 @@ class Enuf:
         _check(lib.enuf_get_timings(self._h, arr, len(PHASES), ctypes.byref(cnt)), self._h)
         return dict(zip(PHASES, list(arr)[: cnt.value]))
 
+    def step_timings(self, cap=4096):
+        """Per-evaluation phase times in ms, shape [evaluations, phases]."""
+        import numpy as np
+
+        lib = load_library()
+        arr = (ctypes.c_double * (cap * len(PHASES)))()
+        cnt = ctypes.c_int32()
+        _check(lib.enuf_get_step_timings(self._h, arr, cap, ctypes.byref(cnt)), self._h)
+        return np.array(arr[: cnt.value * len(PHASES)], dtype=np.float64).reshape(cnt.value, len(PHASES))
+
 
 class EnufEnergy(torch.autograd.Function):
     """E = ENUF energy of (x, q); backward gives the exact dE/dx and dE/dq of
-    the computed energy through the library's adjoint kernels."""
+    the computed energy through the library's adjoint kernels.
+
+    The adjoint reads what the engine kept from its last evaluation.  Each
+    graph node records the evaluation token and the options of its own
+    forward; if the engine has evaluated since (several energies on one
+    engine before one backward), the node evaluates its saved (x, q) again
+    with its own options before the adjoint, so every node gets the gradient
+    of its own configuration.  The upstream gradient stays on the device."""
 
     @staticmethod
     def forward(ctx, x, q, engine):
         E, _, _ = engine.energy_forces(x.detach(), q.detach(), forces=False, potential=True)
         ctx.engine = engine
+        ctx.token = engine.token()
+        ctx.opts = engine.options()
+        ctx.save_for_backward(x, q)
         return E[0].clone()
 
     @staticmethod
     def backward(ctx, gE):
-        g = float(gE.item())
-        dx, dq = ctx.engine.energy_grad(g, dx=ctx.needs_input_grad[0], dq=ctx.needs_input_grad[1])
+        eng = ctx.engine
+        x, q = ctx.saved_tensors
+        token = ctx.token
+        if eng.token() != token:
+            current = eng.options()
+            eng.set_options(ctx.opts)
+            try:
+                eng.energy_forces(x.detach(), q.detach(), forces=False, potential=True)
+                token = eng.token()
+            finally:
+                eng.set_options(current)
+        dx, dq = eng.energy_grad_dev(token, gE, dx=ctx.needs_input_grad[0], dq=ctx.needs_input_grad[1])
         return dx, dq, None
 
 

@@ -135,3 +135,58 @@ def test_forces_only_matches_forces_with_potential(prec):
     assert np.abs(a["E"] - b["E"]).max() <= tol * np.abs(a["E"]).max()
     # neutral sites are active only with potentials; forces on them are zero either way
     assert rms_rel(b["F"], a["F"]) <= tol
+
+
+def test_autograd_two_forwards_then_one_backward():
+    """Two energies on one engine before a single backward: each graph node
+    gets the gradient of its own configuration (the engine's kept state
+    belongs to the second one, so the first node evaluates again)."""
+    x, q, box = _sys(n=700, seed=17)
+    x2 = x + np.random.default_rng(5).normal(0.0, 0.2, x.shape)
+    args = (1.1, 4.0, (32, 32, 32), 6)
+    eng = enuf.Enuf(box, len(q), *args)
+    xa = to_dev(x, torch.float64).requires_grad_(True)
+    xb = to_dev(x2, torch.float64).requires_grad_(True)
+    qt = to_dev(q, torch.float64).requires_grad_(True)
+    Ea = enuf.enuf_energy(xa, qt, eng)
+    Eb = enuf.enuf_energy(xb, qt, eng)
+    (Ea + 2.0 * Eb).backward()
+    ma = em.enuf(x, q, box, *args)
+    mb = em.enuf(x2, q, box, *args)
+    assert rms_rel(xa.grad.cpu().numpy(), ma["grad_x"]) <= 1e-10
+    assert rms_rel(xb.grad.cpu().numpy(), 2.0 * mb["grad_x"]) <= 1e-10
+    assert rms_rel(qt.grad.cpu().numpy(), ma["phi"] + 2.0 * mb["phi"]) <= 1e-10
+
+
+def test_autograd_option_change_between_forward_and_backward():
+    """The gradient belongs to the options of the forward call (here the
+    Coulomb prefactor), whatever is set before backward."""
+    x, q, box = _sys(n=500, seed=18)
+    args = (1.1, 4.0, (32, 32, 32), 6)
+    eng = enuf.Enuf(box, len(q), *args)
+    xt = to_dev(x, torch.float64).requires_grad_(True)
+    qt = to_dev(q, torch.float64)
+    E = enuf.enuf_energy(xt, qt, eng)
+    eng.set_option(enuf.OPT_KE, 2.0)
+    E.backward()
+    m = em.enuf(x, q, box, *args)
+    assert rms_rel(xt.grad.cpu().numpy(), m["grad_x"]) <= 1e-10
+    # and the direct adjoint of an evaluation made with ke = 2 scales by 2
+    eng.energy_forces(to_dev(x, torch.float64), qt, forces=False, potential=True)
+    gx, _ = eng.energy_grad(1.0)
+    assert rms_rel(gx.cpu().numpy(), 2.0 * m["grad_x"]) <= 1e-10
+
+
+def test_grad_dev_rejects_a_stale_token():
+    x, q, box = _sys(n=400, seed=19)
+    eng, _ = run(x, q, box, 1.1, 4.0, (32, 32, 32), 4)
+    t0 = eng.token()
+    g = torch.ones(1, dtype=torch.float64, device="cuda")
+    gx, _ = eng.energy_grad_dev(t0, g)
+    gx_host, _ = eng.energy_grad(1.0)
+    assert torch.equal(gx, gx_host)
+    run(x, q, box, 1.1, 4.0, (32, 32, 32), 4, eng=eng)
+    assert eng.token() == t0 + 1
+    with pytest.raises(enuf.EnufError) as ei:
+        eng.energy_grad_dev(t0, g)
+    assert ei.value.status == enuf.ENUF_ESTATE

@@ -1,0 +1,151 @@
+"""Element-wise GPU parity on the launch shapes the benchmark itself runs.
+
+The one-million-ion benchmark evaluates FP32 analytic-derivative forces on a
+256^3 grid.  That setting takes kernels and launch shapes the small parity
+cases never reach:
+
+  * the z pass that transforms the potential spectrum alone (taken for FP32
+    analytic forces when the z axis has 128 or 256 points);
+  * the FP32 batch sizes of the x and y passes at 128- and 256-point axes
+    (the pencil batch is chosen from the complex element size, so FP32 and
+    FP64 runs of one grid launch differently);
+  * the pair kernel at the benchmark's density (about three charges per unit
+    volume, r_c = 1.8).
+
+Each case is compared with the numpy mirror of the same algorithm
+(``oracle/enuf_mirror.py``, Sec. 2.3.1, Eq. 36-42) element by element: the
+grid stage, every energy part, every force and potential.
+
+Tolerance (FP32).  The mirror is fed the FP32-rounded positions and charges,
+so rounding inside the kernels is all that separates the two.  The grid
+coordinate s = x M / L is formed in FP32: at M = 256 its error is up to
+~2 ulp(256) = 3e-5 grid units, which moves each window weight by at most
+that much times |dB/ds| <= 1, i.e. ~3e-5 of a force's largest stencil term;
+summed over 216 stencil points with random signs and averaged over particles
+that is ~1e-5 relative RMS.  Transforms add ~6e-8 log2(G) ~ 1.5e-6.  The
+same 5e-5 RMS bound as the small FP32 parity cases therefore holds with
+margin, while an indexing or twiddle mistake shows up at O(1).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import enuf_mirror as em  # noqa: E402
+from paper_2004_12484_amd import enuf, inputs  # noqa: E402
+
+from gpu_util import rms_rel, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL32_F = 5e-5
+TOL32_E = 3e-5
+
+
+def _system(n, box, seed, neutral_every=0):
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, float)
+    x = rng.uniform(0.0, 1.0, (n, 3)) * box
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * rng.uniform(0.5, 1.5, n)
+    if neutral_every:
+        q[::neutral_every] = 0.0
+    return x, q, box
+
+
+def _f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def _run(x, q, box, alpha, rc, M, p, mode):
+    eng = enuf.Enuf(box, len(q), alpha, rc, M, p, precision="f32", force_mode=mode)
+    E, F, phi = eng.energy_forces(to_dev(x, eng.dtype), to_dev(q, eng.dtype), potential=True)
+    torch.cuda.synchronize()
+    out = {"E": E.cpu().numpy(), "F": F.double().cpu().numpy(), "phi": phi.double().cpu().numpy()}
+    return eng, out
+
+
+def _check_results(out, m, F_ref):
+    scale = abs(m["E_R"]) + abs(m["E_K"]) + abs(m["E_self"]) + abs(m["E_bg"])
+    for k, name in ((1, "E_R"), (2, "E_K"), (3, "E_self"), (4, "E_bg")):
+        assert abs(out["E"][k] - m[name]) <= TOL32_E * scale, (name, out["E"][k], m[name])
+    assert abs(out["E"][0] - m["E"]) <= TOL32_E * scale
+    eps_f = rms_rel(out["F"], F_ref)
+    eps_p = rms_rel(out["phi"], m["phi"])
+    print(f"eps_F={eps_f:.2e} eps_phi={eps_p:.2e} max|dF|/max|F|="
+          f"{np.abs(out['F'] - F_ref).max() / np.abs(F_ref).max():.2e}")
+    assert eps_f <= TOL32_F
+    assert eps_p <= TOL32_F
+    assert np.abs(out["F"] - F_ref).max() <= 20 * TOL32_F * np.abs(F_ref).max()
+
+
+@pytest.mark.parametrize("M", [(16, 16, 128), (16, 16, 256), (32, 16, 128)])
+def test_analytic_f32_potential_z_pass_vs_mirror(M):
+    """FP32 analytic forces with a 128- or 256-point z axis: the z pass of the
+    potential spectrum alone; psi grid, energies, forces (minus the mirror's
+    exact gradient) and potentials."""
+    box = (7.0, 7.5, 0.45 * M[2])
+    x, q, box = _system(1200, box, seed=M[2] + M[0], neutral_every=9)
+    alpha, rc, p = 1.25, 3.2, 6
+    eng, out = _run(x, q, box, alpha, rc, M, p, "analytic")
+    xr, qr = _f32(x), _f32(q)
+    m = em.enuf(xr, qr, box, alpha, rc, M, p)
+    psi = eng.stage(enuf.STAGE_FIELDS).double().cpu().numpy()
+    assert psi.shape == (M[2], M[1], M[0])
+    tol = 4e-7 * max(M)
+    assert np.abs(psi - m["psi"]).max() <= 20 * tol * np.abs(m["psi"]).max()
+    _check_results(out, m, -m["grad_x"])
+
+
+@pytest.mark.parametrize("M", [(256, 128, 16), (128, 256, 16), (256, 256, 16)])
+def test_ik_f32_long_xy_axes_vs_mirror(M):
+    """FP32 ik forces with 128- and 256-point x and y axes: the FP32 batch
+    sizes of the x (real-to-complex, complex-to-real) and y passes; the
+    spread grid, the half spectrum after the x and y passes, the four field
+    grids and the results."""
+    box = (0.11 * M[0], 0.11 * M[1], 7.0)
+    x, q, box = _system(1500, box, seed=M[0] + 3 * M[1], neutral_every=5)
+    alpha, rc, p = 1.3, 3.1, 4
+    eng, out = _run(x, q, box, alpha, rc, M, p, "ik")
+    xr, qr = _f32(x), _f32(q)
+    m = em.enuf(xr, qr, box, alpha, rc, M, p, want_grad=False)
+    tol = 4e-7 * max(M)
+    grid = eng.stage(enuf.STAGE_GRID).double().cpu().numpy()
+    assert np.abs(grid - m["rho"]).max() <= tol * np.abs(m["rho"]).max()
+    spec = eng.stage(enuf.STAGE_SPECTRUM).double().cpu().numpy()
+    spec = spec[..., 0] + 1j * spec[..., 1]
+    ref = np.fft.fft(np.fft.rfft(m["rho"], axis=2)[:, :, : M[0] // 2], axis=1)
+    assert np.abs(spec - ref).max() <= 5 * tol * np.abs(ref).max()
+    fields = eng.stage(enuf.STAGE_FIELDS).double().cpu().numpy()
+    for c, f in enumerate(m["fields"] + [m["psi"]]):
+        assert np.abs(fields[..., c] - f).max() <= 20 * tol * np.abs(f).max(), c
+    _check_results(out, m, m["F"])
+
+
+def test_bench_grid_analytic_f32_vs_mirror():
+    """The benchmark's own grid and window (256^3, p = 6, FP32, analytic
+    forces, alpha = 2.9/1.8, r_c = 1.8) with 24k charges in its 70^3 box:
+    every kernel and launch shape of a one-million-ion evaluation except the
+    particle counts."""
+    w = inputs.ions_1m()
+    rng = np.random.default_rng(17)
+    sel = rng.choice(w.N, 24000, replace=False)
+    x, q = w.x[sel], w.q[sel]
+    eng, out = _run(x, q, w.box, w.alpha, w.r_c, w.M, w.p, "analytic")
+    xr, qr = _f32(x), _f32(q)
+    m = em.enuf(xr, qr, w.box, w.alpha, w.r_c, w.M, w.p)
+    psi = eng.stage(enuf.STAGE_FIELDS).double().cpu().numpy()
+    tol = 4e-7 * 256
+    assert np.abs(psi - m["psi"]).max() <= 20 * tol * np.abs(m["psi"]).max()
+    _check_results(out, m, -m["grad_x"])
+
+
+def test_bench_density_scaled_analytic_f32_vs_mirror():
+    """The one-million-ion system scaled down at constant density and grid
+    spacing (16384 ions in 17.5^3, M = 64^3, p = 6, the benchmark's alpha and
+    r_c): the pair kernel sees the benchmark's neighbour counts (~75 charges
+    inside r_c) and the window the same alpha h."""
+    w = inputs.ions_1m(N=16384, L=17.5, M=64)
+    eng, out = _run(w.x, w.q, w.box, w.alpha, w.r_c, w.M, w.p, "analytic")
+    xr, qr = _f32(w.x), _f32(w.q)
+    m = em.enuf(xr, qr, w.box, w.alpha, w.r_c, w.M, w.p)
+    _check_results(out, m, -m["grad_x"])
