@@ -228,6 +228,37 @@ enuf_status enuf_eval_token(enuf_ctx ctx, uint64_t *token);
 enuf_status enuf_energy_grad_dev(enuf_ctx ctx, uint64_t token, const double *grad_E, void *dEdx,
                                  void *dEdq);
 
+/* Bytes of the static device scratch enuf_energy_forces_noalloc() works in
+ * (64 MiB per GPU). */
+#define ENUF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * enuf_energy_forces_noalloc -- enuf_energy_forces() for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same evaluation, kernels and outputs,
+ * but its working memory is a static device array of the library
+ * (ENUF_NOALLOC_SCRATCH_BYTES per GPU, created when the library's code object
+ * is loaded onto a GPU and held until the process ends), not the context's
+ * workspace; the context needs no workspace.  The call allocates and frees
+ * nothing; the caller still provides x, q, E, F and phi as for
+ * enuf_energy_forces().
+ *   Size limit: ENUF_EUNSUPPORTED (with the byte counts in
+ *   enuf_last_error) when the context's enuf_workspace_bytes() exceeds
+ *   ENUF_NOALLOC_SCRATCH_BYTES (e.g. 32768 particles on a 64^3 grid in FP64
+ *   fit; a million particles on 256^3 do not).
+ *   Sharing: every call on one GPU uses that GPU's one scratch array, and
+ *   each call re-initialises it (tables, counters, flags, energy slots) on
+ *   the context's stream before evaluating.  Calls whose device work
+ *   overlaps on one GPU (different streams or host threads without ordering)
+ *   race on the scratch and give wrong results; order them on one stream.
+ *   It does not change the context's adjoint state: enuf_energy_grad() and
+ *   enuf_eval_token() still refer to the last enuf_energy_forces() on the
+ *   context.  ENUF_OPT_GRAPH and ENUF_OPT_TIMING do not apply (kernels are
+ *   launched one by one, no events recorded); ENUF_OPT_CHECK does.
+ */
+enuf_status enuf_energy_forces_noalloc(enuf_ctx ctx, const void *x, const void *q, double *E,
+                                       void *F, void *phi);
+
 /* enuf_get_flags -- synchronise the stream and return the sticky device
  * flags (bit 0: non-finite input seen); clears them. */
 enuf_status enuf_get_flags(enuf_ctx ctx, int32_t *flags);

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,13 @@
 
 using enuf::Geom;
 using enuf::Work;
+
+// Device scratch of enuf_energy_forces_noalloc: one block per GPU, part of the
+// library's code object (no allocation call creates it), held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address on the current GPU comes from hipGetSymbolAddress, taken once per
+// device (scratch_address) and used wherever host code needs the memory.
+static __device__ __align__(256) unsigned char scratch[ENUF_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -33,6 +41,25 @@ struct GraphCache {
   bool analytic = false;
   double ke = 0.0, slater = 0.0;
 };
+
+constexpr size_t kScratchBytes = ENUF_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU `dev`, which must be the current device.
+hipError_t scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -472,6 +499,39 @@ enuf_status enuf_energy_forces(enuf_ctx ctx, const void *x, const void *q, doubl
   if (ctx->check) {
     int32_t f = 0;
     enuf_status s = read_flags_at(ctx, ctx->w.counts, &f, true);
+    if (s != ENUF_OK) return s;
+    if (f & 1) return fail(ctx, ENUF_ENONFINITE, "non-finite position or charge (excluded from the sums)");
+  }
+  return ENUF_OK;
+}
+
+enuf_status enuf_energy_forces_noalloc(enuf_ctx ctx, const void *x, const void *q, double *E, void *F,
+                                       void *phi) {
+  if (!ctx) return fail(nullptr, ENUF_EINVAL, "ctx is NULL");
+  if (!x || !q || !E) return fail(ctx, ENUF_EINVAL, "x, q and E must not be NULL");
+  const size_t need = layout(ctx->g, real_bytes(ctx), nullptr, nullptr);
+  if (need > kScratchBytes)
+    return fail(ctx, ENUF_EUNSUPPORTED, "enuf_energy_forces_noalloc: this context needs " + std::to_string(need) +
+                                            " bytes of working memory, more than the library's static scratch of " +
+                                            std::to_string(kScratchBytes) + " bytes");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  void *base = nullptr;
+  e = scratch_address(ctx->device, &base);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipGetSymbolAddress(scratch)");
+  // The scratch holds whatever the last call on this GPU left: lay this
+  // context's buffers over it and initialise them (tables, run table, cleared
+  // counters, flags and energy slots) before the evaluation, on the stream.
+  Work w;
+  layout(ctx->g, real_bytes(ctx), (char *)base, &w);
+  w.nruns = ctx->nruns;
+  e = enuf::launch_init_ws(ctx->g, w, ctx->st, ctx->prec == ENUF_FP64);
+  if (e != hipSuccess) return hip_fail(ctx, e, "scratch initialisation");
+  e = forward(ctx, w, ctx->st, x, q, E, F, phi, phi != nullptr, ctx->analytic, nullptr);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+  if (ctx->check) {
+    int32_t f = 0;
+    enuf_status s = read_flags_at(ctx, w.counts, &f, true);
     if (s != ENUF_OK) return s;
     if (f & 1) return fail(ctx, ENUF_ENONFINITE, "non-finite position or charge (excluded from the sums)");
   }

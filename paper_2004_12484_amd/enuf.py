@@ -26,7 +26,7 @@ PHASES = ("prep", "sort", "spread", "fft_fwd", "influence_z", "fft_inv", "gather
 # every symbol include/enuf.h declares
 EXPORTS = (
     "enuf_create", "enuf_workspace_bytes", "enuf_set_workspace", "enuf_alloc_workspace", "enuf_destroy",
-    "enuf_set_option", "enuf_set_stream", "enuf_energy_forces",
+    "enuf_set_option", "enuf_set_stream", "enuf_energy_forces", "enuf_energy_forces_noalloc",
     "enuf_energy_grad", "enuf_eval_token", "enuf_energy_grad_dev", "enuf_get_flags", "enuf_stage_copy",
     "enuf_stage_bytes", "enuf_get_timings", "enuf_get_step_timings", "enuf_status_string", "enuf_last_error",
     "enuf_device_count",
@@ -59,6 +59,7 @@ def load_library():
     lib.enuf_set_option.argtypes = [vp, i32, d]
     lib.enuf_set_stream.argtypes = [vp, vp]
     lib.enuf_energy_forces.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.enuf_energy_forces_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.enuf_energy_grad.argtypes = [vp, d, vp, vp]
     lib.enuf_eval_token.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.enuf_energy_grad_dev.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
@@ -205,6 +206,18 @@ class Enuf:
         _check(load_library().enuf_energy_forces(self._h, _ptr(x), _ptr(q), _ptr(E), _ptr(F), _ptr(phi)),
                self._h)
         self._keep = (x, q)
+        return E, F, phi
+
+    def energy_forces_noalloc(self, x, q, E, F=None, phi=None):
+        """enuf_energy_forces_noalloc: one evaluation in the library's static
+        device scratch (no device allocation by the library; the outputs E,
+        F, phi are the caller's preallocated tensors).  The engine's adjoint
+        state is not changed."""
+        x = self._in(x, (self.n, 3))
+        q = self._in(q, (self.n,))
+        self._bind_stream()
+        _check(load_library().enuf_energy_forces_noalloc(self._h, _ptr(x), _ptr(q), _ptr(E), _ptr(F), _ptr(phi)),
+               self._h)
         return E, F, phi
 
     def token(self):
