@@ -45,6 +45,8 @@ def _load():
         lib.oracle_real_images.argtypes = [i64, vp, vp, vp, d, d, d, vp, vp, vp]
         lib.oracle_real_minimage.argtypes = [i64, vp, vp, vp, d, d, d, i64, vp, vp, vp, vp]
         lib.oracle_real_minimage.restype = ctypes.c_int
+        lib.oracle_real_cells_energy.argtypes = [i64, vp, vp, vp, d, d, d, vp]
+        lib.oracle_real_cells_energy.restype = ctypes.c_int
         lib.oracle_recip.restype = ctypes.c_int
         lib.oracle_recip.argtypes = [i64, vp, vp, vp, d, d, vp, d, i64, vp, vp, vp, vp]
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -102,6 +104,24 @@ def real_minimage(x, q, box, alpha, rc, ke=1.0, sample=None, energy=True):
     if rc_ != 0:
         raise MemoryError("oracle_real_minimage: allocation failed")
     return (float(e[0]) if energy else float("nan")), f, phi
+
+
+def real_energy_cells(x, q, box, alpha, rc, ke=1.0):
+    """Real-space pair energy (Eq. 17, minimum image) over all charged
+    pairs, the pairs enumerated with a linked-cell list (at least 3 cells
+    per axis; otherwise the all-pairs loop of real_minimage).  Same sum as
+    real_minimage's energy, in another order: for systems too large for the
+    all-pairs loop."""
+    x, q, box = _prep(x, q, box)
+    if rc > 0.5 * box.min() * (1 + 1e-12):
+        raise ValueError("minimum image needs rc <= min(L)/2")
+    e = np.zeros(1)
+    rc_ = _load().oracle_real_cells_energy(x.shape[0], _p(x), _p(q), _p(box), alpha, rc, ke, _p(e))
+    if rc_ == -2:
+        return real_minimage(x, q, box, alpha, rc, ke, sample=np.zeros(0, np.int64))[0]
+    if rc_ != 0:
+        raise MemoryError("oracle_real_cells_energy: allocation failed")
+    return float(e[0])
 
 
 def kset_converged(box, alpha, tol=1e-16):

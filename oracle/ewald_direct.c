@@ -160,6 +160,106 @@ int oracle_real_minimage(int64_t n, const double *x, const double *q,
     return 0;
 }
 
+/*
+ * Real-space pair energy E_R (Eq. 17, minimum image, rc <= min(L)/2) over all
+ * charged pairs, the pairs found through a cell list instead of the
+ * all-pairs loop of oracle_real_minimage (same pair term, same result up to
+ * the order of the sum).  The box is cut into nc_d = floor(L_d / rc) cells per
+ * axis; with nc_d >= 3 every pair closer than rc lies in the same or an
+ * adjacent cell, and the 27 neighbour cells of a cell are distinct.  The
+ * charged particles are copied in cell order (counting sort), and each one
+ * visits the particles after it in that order within its 27 neighbour
+ * cells, so every pair is taken once.  Returns -2 when some axis has fewer
+ * than 3 cells (use the all-pairs loop), -1 when an allocation fails.
+ */
+int oracle_real_cells_energy(int64_t n, const double *x, const double *q,
+                             const double box[3], double alpha, double rc, double ke,
+                             double *e_out) {
+    int nc[3];
+    for (int d = 0; d < 3; ++d) {
+        double c = floor(box[d] / rc);
+        if (c < 3.0) return -2;
+        nc[d] = c > 512.0 ? 512 : (int)c;
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t *start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *cid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    double *xs = (double *)malloc(sizeof(double) * 4 * (size_t)(n ? n : 1));
+    if (!start || !cid || !xs) {
+        free(start); free(cid); free(xs);
+        return -1;
+    }
+    /* cell of each charged particle from its wrapped position; counts */
+    for (int64_t i = 0; i < n; ++i) {
+        cid[i] = -1;
+        if (q[i] == 0.0) continue;
+        int k[3];
+        for (int d = 0; d < 3; ++d) {
+            double u = x[3 * i + d] / box[d];
+            u -= floor(u);
+            k[d] = (int)(u * nc[d]);
+            if (k[d] >= nc[d]) k[d] = nc[d] - 1;
+            if (k[d] < 0) k[d] = 0;
+        }
+        cid[i] = ((int64_t)k[2] * nc[1] + k[1]) * nc[0] + k[0];
+        start[cid[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    /* copy (x, y, z, q) in cell order; fill[c] walks each cell's range */
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    if (!fill) {
+        free(start); free(cid); free(xs);
+        return -1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) fill[c] = start[c];
+    for (int64_t i = 0; i < n; ++i) {
+        if (cid[i] < 0) continue;
+        int64_t s = fill[cid[i]]++;
+        xs[4 * s] = x[3 * i];
+        xs[4 * s + 1] = x[3 * i + 1];
+        xs[4 * s + 2] = x[3 * i + 2];
+        xs[4 * s + 3] = q[i];
+    }
+    free(fill);
+    const double rc2 = rc * rc;
+    double etot = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : etot)
+    for (int64_t c = 0; c < ncell; ++c) {
+        const int cx0 = (int)(c % nc[0]);
+        const int cy0 = (int)((c / nc[0]) % nc[1]);
+        const int cz0 = (int)(c / ((int64_t)nc[0] * nc[1]));
+        double ec = 0.0;
+        for (int64_t s = start[c]; s < start[c + 1]; ++s) {
+            const double *pi = xs + 4 * s;
+            for (int a = -1; a <= 1; ++a)
+                for (int b = -1; b <= 1; ++b)
+                    for (int e = -1; e <= 1; ++e) {
+                        int cx = (cx0 + a + nc[0]) % nc[0];
+                        int cy = (cy0 + b + nc[1]) % nc[1];
+                        int cz = (cz0 + e + nc[2]) % nc[2];
+                        int64_t nb = ((int64_t)cz * nc[1] + cy) * nc[0] + cx;
+                        int64_t t0 = start[nb] > s ? start[nb] : s + 1;
+                        for (int64_t t = t0; t < start[nb + 1]; ++t) {
+                            const double *pj = xs + 4 * t;
+                            double dd[3];
+                            for (int k = 0; k < 3; ++k) {
+                                double u = pi[k] - pj[k];
+                                dd[k] = u - box[k] * nearbyint(u / box[k]);
+                            }
+                            double r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+                            if (r2 >= rc2) continue;
+                            double r = sqrt(r2);
+                            ec += ke * pi[3] * pj[3] * erfc(alpha * r) / r;
+                        }
+                    }
+        }
+        etot += ec;
+    }
+    *e_out = etot;
+    free(start); free(cid); free(xs);
+    return 0;
+}
+
 /* exp(-i * 2 pi * m * u) for m = m0 .. m0+cnt-1 (u = r/L in [0,1)); the
  * argument is reduced to a fraction of a turn before cos/sin. */
 static void phase_row(double u, int m0, int cnt, double *re, double *im) {
