@@ -1,6 +1,7 @@
 """Write stored oracle values for the benchmark workloads.
 
     python tests/golden/make_oracle_golden.py [workload ...]
+    python tests/golden/make_oracle_golden.py ions_1m:energy   (adds energies)
 
 Calls only the oracle (the direct FP64 Ewald sum, oracle/ewald.py, and the
 ENUF-DPD smeared real-space sum, oracle/dpd.py) on the seeded synthetic
@@ -58,6 +59,47 @@ def make_forces(name):
     print(f"{name}: forces on {len(sample)} sampled ions, oracle {dt:.1f} s -> {path}", flush=True)
 
 
+# Energies for the force-only workloads.  E_conv is the converged Coulomb
+# energy, the Ewald sum at the oracle's splitting alpha_o with the real-space
+# cut where erfc(alpha_o r) < 1e-10 (pairs through the oracle's cell list) and
+# the k-space sum to tol.  The Ewald energy at a method setting (alpha, r_c)
+# with a converged k-space sum differs from it only by the real-space pairs
+# the cutoff drops:
+#     E(alpha, r_c) = E_conv - sum_{r_c <= r} q_i q_j erfc(alpha r)/r,
+# the tail summed out to erfc(alpha r) < 1e-12.  One row (alpha, r_c, E) per
+# setting: the bench setting and the search grid of the benchmark.
+ENERGY_SETTINGS = {
+    "ions_1m": [(2.9 / 1.8, 1.8)] + [(arc / rc, rc) for rc in (1.5, 1.8, 2.1, 2.4, 2.7, 3.0)
+                                       for arc in (2.6, 2.9, 3.2)],
+    # the stated 256 x 256 x 512 grid's setting
+    "anisotropic": [(0.8, 4.0)],
+}
+
+
+def make_energies(name):
+    kw, _, alpha_o, tol = FORCE_ONLY[name]
+    w = getattr(inputs, name)(**kw)
+    path = os.path.join(HERE, f"{name}_oracle.npz")
+    g = dict(np.load(path))
+    assert int(g["N"]) == w.N and int(g["seed"]) == w.seed
+    t = time.time()
+    rc_o = min(0.5 * float(np.min(w.box)), 4.6 / alpha_o)
+    e_r = ewald.real_energy_cells(w.x, w.q, w.box, alpha_o, rc_o, w.ke)
+    e_k, _, _ = ewald.recip(w.x, w.q, w.box, alpha_o, w.ke, tol=tol, sample=np.zeros(0, np.int64))
+    e_s, e_b, _, _ = ewald.self_terms(w.q, w.box, alpha_o, w.ke)
+    e_conv = e_r + e_k + e_s + e_b
+    rows = []
+    for alpha, rc in dict.fromkeys(ENERGY_SETTINGS[name]):
+        r_far = min(0.5 * float(np.min(w.box)), 5.0 / alpha)
+        tail = (ewald.real_energy_cells(w.x, w.q, w.box, alpha, r_far, w.ke)
+                - ewald.real_energy_cells(w.x, w.q, w.box, alpha, rc, w.ke))
+        rows.append((alpha, rc, e_conv - tail))
+    g.update(E_conv=e_conv, E_table=np.array(rows, np.float64))
+    np.savez_compressed(path, **g)
+    print(f"{name}: E_conv={e_conv:.12g} and {len(rows)} settings, oracle {time.time() - t:.1f} s -> {path}",
+          flush=True)
+
+
 # ENUF-DPD: the charged fluid as a DPD system (R_c = 1, density ~3,
 # real-space cutoff 3 R_c) of Slater-smeared charges with beta = 1.125: the
 # stored point-charge k-space forces with the smeared real-space sum
@@ -105,8 +147,11 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(SPECS) + list(FORCE_ONLY) + list(SLATER)):
-        if n in FORCE_ONLY:
+    default = list(SPECS) + list(FORCE_ONLY) + [f"{n}:energy" for n in ENERGY_SETTINGS] + list(SLATER)
+    for n in (sys.argv[1:] or default):
+        if n.endswith(":energy"):
+            make_energies(n.split(":")[0])
+        elif n in FORCE_ONLY:
             make_forces(n)
         elif n in SLATER:
             make_slater(n)
