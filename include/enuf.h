@@ -286,6 +286,47 @@ enuf_status enuf_get_timings(enuf_ctx ctx, double *ms, int32_t n, int32_t *count
  * enuf_get_timings(). */
 enuf_status enuf_get_step_timings(enuf_ctx ctx, double *ms, int32_t cap, int32_t *count);
 
+/* How enuf_select_params chose (its `method` output). */
+enum { ENUF_SELECT_HEURISTIC = 0, ENUF_SELECT_NETWORK = 1 };
+
+/*
+ * enuf_select_params -- ENUF parameters (alpha, r_c, grid M, window p) for a
+ * system and a target RMS relative force error (paper Sec. 2.3.2: the error
+ * relations of Eq. 31-32 and the choice of the reciprocal cutoff n_c).
+ *   box            host double[3] box lengths > 0
+ *   n              number of particles >= 2
+ *   charged_frac   fraction of charged particles, in (0, 1]
+ *   target_rms_err target RMS relative force error, in (0, 1)
+ *   model_path     NULL: the heuristic.  Else the trained parameter network
+ *                  (file written by the package's training script): when
+ *                  the system lies inside the ranges it was trained on (N,
+ *                  density, charged fraction, target, box shape, all stored
+ *                  in the file) its prediction is evaluated on the current
+ *                  HIP device with enuf_mlp_forward and snapped to a valid
+ *                  setting; outside them the heuristic is used.
+ *   alpha, r_c     out (host): splitting parameter and real-space cutoff
+ *                  (r_c <= min(L)/2)
+ *   M              out (host int32[3]): grid, powers of two in [8, 512]
+ *   p              out (host): window width (4, 6 or 8 with 2p <= M)
+ *   method         out (host, may be NULL): ENUF_SELECT_HEURISTIC or
+ *                  ENUF_SELECT_NETWORK
+ * Heuristic: alpha and r_c from Eq. 31 and 32 at equality,
+ * exp(-pi^2 n_c^2/(alpha L_x)^2) = exp(-alpha^2 r_c^2) = target, with n_c
+ * raised from 2 until r_c <= min(3 a, min(L)/2) (a = (V/N)^(1/3), the mean
+ * spacing); every mode up to n_c is kept on each axis; p = 6.
+ * Network evaluation allocates (and frees) a small device buffer and
+ * synchronises.  Errors: ENUF_EINVAL for bad arguments or an unreadable or
+ * malformed network file, ENUF_EDEVICE/ENUF_ENOMEM for device failures; the
+ * text is in enuf_select_last_error().
+ */
+enuf_status enuf_select_params(const double box[3], int64_t n, double charged_frac,
+                               double target_rms_err, const char *model_path, double *alpha,
+                               double *r_c, int32_t M[3], int32_t *p, int32_t *method);
+
+/* enuf_select_last_error -- text of the last enuf_select_params error on
+ * this host thread. */
+const char *enuf_select_last_error(void);
+
 /* enuf_status_string -- static text for a status code. */
 const char *enuf_status_string(enuf_status s);
 

@@ -29,7 +29,7 @@ EXPORTS = (
     "enuf_set_option", "enuf_set_stream", "enuf_energy_forces", "enuf_energy_forces_noalloc",
     "enuf_energy_grad", "enuf_eval_token", "enuf_energy_grad_dev", "enuf_get_flags", "enuf_stage_copy",
     "enuf_stage_bytes", "enuf_get_timings", "enuf_get_step_timings", "enuf_status_string", "enuf_last_error",
-    "enuf_device_count",
+    "enuf_device_count", "enuf_select_params", "enuf_select_last_error",
 )
 
 _lib = None
@@ -73,8 +73,12 @@ def load_library():
     lib.enuf_last_error.argtypes = [vp]
     lib.enuf_last_error.restype = ctypes.c_char_p
     lib.enuf_device_count.restype = i32
+    lib.enuf_select_params.argtypes = [ctypes.POINTER(d), i64, d, d, ctypes.c_char_p, ctypes.POINTER(d),
+                                       ctypes.POINTER(d), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
+    lib.enuf_select_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("enuf_status_string", "enuf_last_error", "enuf_device_count"):
+        if name not in ("enuf_status_string", "enuf_last_error", "enuf_device_count", "enuf_select_last_error"):
             getattr(lib, name).restype = i32
     _lib = lib
     return lib

@@ -74,6 +74,7 @@ def train(paths, epochs=300, seed=0, log=print):
     os.makedirs(os.path.dirname(P.MODEL_PATH), exist_ok=True)
     np.savez(P.MODEL_PATH, params=net.numpy_params(), x_mean=xm, x_std=xs, y_mean=ym, y_std=ys,
              dims=np.array([5, 64, 3, 6]), loss=np.array(hist), n_train=len(Xtr))
+    P.export_bin(P.MODEL_PATH)
     return hist
 
 

@@ -56,6 +56,25 @@ def test_sweep_reference_matches_oracle():
 
 
 @pytest.mark.skipif(not os.path.exists(P.MODEL_PATH), reason="trained parameter model not present")
+def test_library_selection_equals_network_prediction():
+    """enuf_select_params with the network file gives the network's own
+    prediction (forward kernel through the Python binding), snapped."""
+    pred = P.Predictor()
+    rng = np.random.default_rng(7)
+    for k in range(40):
+        w = inputs.random_system(300 + k)
+        fq = float(np.count_nonzero(w.q)) / w.N
+        tgt = float(10 ** rng.uniform(-4.5, -3))
+        s, method = P.select_params(w.N, w.box, fq, tgt, model_path=P.MODEL_BIN)
+        assert method == "network"
+        y = pred.predict_raw(P.features(w.N, w.box, fq, tgt))[0]
+        ref = P.snap(w.box, w.N, y[0], y[1:4], y[4], y[5])
+        assert s["M"] == ref["M"] and s["p"] == ref["p"], (s, ref)
+        assert abs(s["alpha"] - ref["alpha"]) <= 1e-6 * ref["alpha"]
+        assert abs(s["r_c"] - ref["r_c"]) <= 1e-6 * ref["r_c"]
+
+
+@pytest.mark.skipif(not os.path.exists(P.MODEL_PATH), reason="trained parameter model not present")
 def test_trained_network_meets_targets_on_fresh_systems():
     pred = P.Predictor()
     hits = {1e-3: 0, 1e-4: 0}

@@ -73,3 +73,36 @@ def test_combine_separable_rows():
     best = P.grid_search({"settings": s}, 2e-4)
     assert best is not None and best["alpha"] == 2.0
     assert P.grid_search({"settings": s}, 1e-6) is None
+
+
+def test_select_params_rejects_bad_arguments():
+    from paper_2004_12484_amd import enuf
+
+    box = [20.0, 20.0, 20.0]
+    for args in ((1, box, 0.5, 1e-4), (1000, box, 0.0, 1e-4), (1000, box, 0.5, 0.0), (1000, [20, -1, 20], 0.5, 1e-4)):
+        with pytest.raises(enuf.EnufError) as ei:
+            P.select_params(*args)
+        assert ei.value.status == enuf.ENUF_EINVAL
+
+
+def test_select_params_network_file_checks(tmp_path):
+    """A malformed network file is refused; a valid one is not evaluated for
+    a system outside its training ranges (the heuristic is used, no GPU)."""
+    from paper_2004_12484_amd import enuf
+
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTANET!" + b"\0" * 64)
+    with pytest.raises(enuf.EnufError) as ei:
+        P.select_params(5000, [20.0, 20.0, 20.0], 0.5, 1e-4, model_path=str(bad))
+    assert ei.value.status == enuf.ENUF_EINVAL
+    with pytest.raises(enuf.EnufError):
+        P.select_params(5000, [20.0, 20.0, 20.0], 0.5, 1e-4, model_path=str(tmp_path / "missing.bin"))
+    good = P.export_bin(P.MODEL_PATH, out=str(tmp_path / "net.bin"))
+    box = [200.0, 200.0, 200.0]
+    N = 20_000_000   # above the training range
+    s, method = P.select_params(N, box, 0.5, 1e-4, model_path=good)
+    assert method == "heuristic"
+    assert s == P.heuristic(N, box, 0.5, 1e-4)
+    # a 1:2:1 box is not a trained shape (the network saw 1:1:1 and 1:1:2)
+    assert not P.in_training_range(20000, [20.0, 40.0, 20.0], 0.5, 1e-4)
+    assert P.in_training_range(20000, [20.0, 20.0, 40.0], 0.5, 1e-4)
