@@ -36,7 +36,10 @@ PAIR_FLOPS = 40.0              # flops per evaluated pair (erfc, exp, rsqrt, acc
 # systems.
 WORKLOADS = {
     "charged_fluid": dict(gen="charged_fluid", kw=dict(alpha=0.95)),
-    "ions_1m": dict(gen="ions_1m", kw={}, force_mode="analytic"),
+    "ions_1m": dict(gen="ions_1m", kw={}, force_mode="analytic",
+                    # the plain FP64 form's fastest setting with eps_F <= 1e-4
+                    # (bench.py --search --precision f64: 3.02 ms, eps_F 4.9e-5)
+                    fp64_form=dict(force_mode="analytic", M=(256, 256, 256), p=6, r_c=1.8, alpha=2.9 / 1.8)),
     "electrolyte": dict(gen="electrolyte", kw={}),
     "nacl": dict(gen="nacl", kw={}),
     # 4M sites in 120 x 120 x 240: parameters from the selector (the network,
@@ -44,7 +47,11 @@ WORKLOADS = {
     # network's training range) at the FP32 form's accuracy bar 5e-4 (FP32
     # rounding of the positions alone costs ~2.8e-4 here: chain beads come
     # within a few hundredths of each other), forces and dE/dq
-    "anisotropic": dict(gen="anisotropic", kw={}, select=5e-4, potential=True),
+    "anisotropic_selected": dict(gen="anisotropic", kw={}, select=5e-4, potential=True, golden="anisotropic"),
+    # the same system at its stated grid, 256 x 256 x 512 with p = 6; alpha
+    # and r_c the fastest of a timed sweep at that grid (alpha r_c in 2.6 ..
+    # 3.5, r_c in 2.5 .. 4.5; every setting met 1e-4 against the oracle)
+    "anisotropic": dict(gen="anisotropic", kw=dict(alpha=0.8, r_c=4.0, M=(256, 256, 512), p=6), potential=True),
     # ENUF-DPD: the charged fluid read as a DPD system (R_c = 1, density ~3,
     # real-space cutoff 3 R_c) of Slater-smeared charges with beta = 1.125
     # (decay length 1/1.125)
@@ -178,8 +185,16 @@ def golden_check(w, F, E, phi=None, name=None):
         # against the Ewald sum with the real-space cut converged
         out["rms_force_err_rc_converged"] = float(np.linalg.norm(Fs - g["F_conv"]) / np.linalg.norm(g["F_conv"]))
         out.setdefault("rms_force_err", out["rms_force_err_rc_converged"])
-    if "E" in g.files:
+    if "E" in g.files and np.isclose(float(g["alpha"]), w.alpha) and np.isclose(float(g["r_c"]), w.r_c):
         out["energy_rel_err"] = float(abs(E - float(g["E"])) / abs(float(g["E"])))
+    if "E_table" in g.files:
+        # Ewald energy at this (alpha, r_c), stored per setting
+        for a, rc, e_ref in g["E_table"]:
+            if np.isclose(a, w.alpha) and np.isclose(rc, w.r_c):
+                out["energy_rel_err"] = float(abs(E - e_ref) / abs(e_ref))
+    if "E_conv" in g.files:
+        # against the converged Coulomb energy (alpha-independent)
+        out["energy_rel_err_conv"] = float(abs(E - float(g["E_conv"])) / abs(float(g["E_conv"])))
     if phi is not None and ("phi_conv" in g.files or "phi" in g.files):
         # dE/dq against the (converged) potentials
         ref = g["phi_conv"] if "phi_conv" in g.files else g["phi"]
@@ -187,14 +202,49 @@ def golden_check(w, F, E, phi=None, name=None):
     return out
 
 
+def fp64_form(w, setting, x32, q32, args, name):
+    """The plain FP64 form of the same workload at its own fastest setting
+    meeting the same force-error bar (from `bench.py --search --precision
+    f64`), timed like the main line over the same number of steps: the
+    comparison the FP32 form has to win at equal stated accuracy."""
+    import copy
+
+    import torch
+
+    from paper_2004_12484_amd import enuf
+
+    w64 = copy.copy(w)
+    w64.alpha, w64.r_c, w64.M, w64.p = setting["alpha"], setting["r_c"], tuple(setting["M"]), setting["p"]
+    x = torch.tensor(w.x, dtype=torch.float64, device=x32.device)
+    q = torch.tensor(w.q, dtype=torch.float64, device=x32.device)
+    eng = enuf.Enuf(w64.box, w64.N, w64.alpha, w64.r_c, w64.M, w64.p, precision="f64", device=x32.device,
+                    force_mode=setting["force_mode"])
+    for _ in range(args.warmup):
+        E, F, _ = eng.energy_forces(x, q)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        E, F, _ = eng.energy_forces(x, q)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    acc = golden_check(w64, F.cpu().numpy(), float(E[0].item()), name=name)
+    eng.close()
+    return {"ms_per_step": ms, "value": 1000.0 / ms, "unit": "evals/s", "dtype": "f64",
+            "setting": dict(setting), "accuracy": acc}
+
+
 SEARCH_GRID = dict(mode=("ik", "analytic"), M=(128, 256), p=(4, 6), r_c=(1.5, 1.8, 2.1, 2.4, 2.7, 3.0),
                    alpha_rc=(2.6, 2.9, 3.2))
 
 
 def search(args, target=1e-4, steps=5):
-    """Grid search over ENUF settings for one workload (FP32): each setting is
-    timed over `steps` evaluations (HIP events around the calls) and its RMS
-    force error taken against the stored oracle forces."""
+    """Grid search over ENUF settings for one workload (FP32 unless
+    --precision says otherwise): each setting is timed over `steps`
+    evaluations (HIP events around the calls) and its RMS force error taken
+    against the stored oracle forces."""
     import itertools
 
     import torch
@@ -204,14 +254,16 @@ def search(args, target=1e-4, steps=5):
     spec = WORKLOADS[args.workload]
     w0 = getattr(inputs, spec["gen"])(**spec["kw"])
     dev = torch.device("cuda", 0)
-    x = torch.tensor(w0.x, dtype=torch.float32, device=dev)
-    q = torch.tensor(w0.q, dtype=torch.float32, device=dev)
+    prec = args.precision or "f32"
+    dt = torch.float64 if prec == "f64" else torch.float32
+    x = torch.tensor(w0.x, dtype=dt, device=dev)
+    q = torch.tensor(w0.q, dtype=dt, device=dev)
     best = None
     for mode, M, p, rc, arc in itertools.product(*SEARCH_GRID.values()):
         if rc > 0.5 * float(np.min(w0.box)):
             continue
         alpha = arc / rc
-        eng = enuf.Enuf(w0.box, w0.N, alpha, rc, (M, M, M), p, precision="f32", device=dev, force_mode=mode)
+        eng = enuf.Enuf(w0.box, w0.N, alpha, rc, (M, M, M), p, precision=prec, device=dev, force_mode=mode)
         for _ in range(2):
             E, F, _ = eng.energy_forces(x, q)
         torch.cuda.synchronize()
@@ -227,11 +279,13 @@ def search(args, target=1e-4, steps=5):
         w0.alpha, w0.r_c, w0.M, w0.p = alpha, rc, (M, M, M), p
         acc = golden_check(w0, F.double().cpu().numpy(), float(E[0].item()))
         err = acc["rms_force_err"] if acc else None
-        rec = {"force_mode": mode, "M": M, "p": p, "r_c": rc, "alpha": alpha, "ms": ms, "rms_force_err": err}
+        rec = {"precision": prec, "force_mode": mode, "M": M, "p": p, "r_c": rc, "alpha": alpha, "ms": ms,
+               "rms_force_err": err, "energy_rel_err": acc.get("energy_rel_err") if acc else None}
         print(json.dumps(rec), flush=True)
         if err is not None and err <= target and (best is None or ms < best["ms"]):
             best = rec
-    print(json.dumps({"search_best": best, "target": target, "workload": args.workload}), flush=True)
+    print(json.dumps({"search_best": best, "target": target, "workload": args.workload, "precision": prec}),
+          flush=True)
 
 
 def main():
@@ -249,6 +303,8 @@ def main():
                     help="reciprocal forces: ik fields (three inverse transforms) or the analytic window "
                          "derivative (one); default: the workload's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-form", action="store_true",
+                    help="skip timing the plain FP64 form of the workload beside the main line")
     ap.add_argument("--search", action="store_true",
                     help="grid-search (alpha, r_c, M, p) for the workload: time each FP32 setting and its "
                          "RMS force error against the stored oracle forces; print one JSON line per setting")
@@ -347,7 +403,7 @@ def main():
     Eh = E.cpu().numpy()
     Fh = F.double().cpu().numpy()
     acc = golden_check(w, Fh, float(Eh[0]), phi.double().cpu().numpy() if phi is not None else None,
-                       name=args.workload)
+                       name=spec.get("golden", args.workload))
 
     # roofline of the dominant phase
     analytic = force_mode == "analytic"
@@ -389,6 +445,8 @@ def main():
                    "background": float(Eh[4])},
         "accuracy": acc, "roofline": roof,
     }
+    if spec.get("fp64_form") and not args.no_fp64_form and w.precision == "f32":
+        rec["fp64_form"] = fp64_form(w, spec["fp64_form"], x, q, args, name=spec.get("golden", args.workload))
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
