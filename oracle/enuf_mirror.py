@@ -35,6 +35,15 @@ Readings of the paper taken here (where it is silent or ambiguous):
     transform sinc^p(pi n/M) (the NFFT scaling step) or, optionally, its
     discrete Fourier transform on the grid.
   * Boxes are orthorhombic (the paper writes the cubic case).
+  * The paper's own NFFT (Sec. 2.2, 2.3.2; CU-NFFT, Sec. 3.1) oversamples
+    and uses a Gaussian window: the optional form here keeps only the modes
+    |n_d| < K_d/2 of the M_d-point grid, K_d = 2 floor(M_d / (2 sigma_s))
+    (oversampling factor sigma_s = M_d/K_d >= 1), and weights the stencil
+    points floor(s) - m .. floor(s) + m + 1 (p = 2m + 2 of them, the NFFT
+    library's support for cutoff m) by exp(-(s - l)^2 / b) with that
+    library's Gaussian shape b = 2 sigma_s m / ((2 sigma_s - 1) pi); its
+    scaling step divides by the continuous Fourier transform
+    sqrt(pi b) exp(-b (pi n / M)^2).
 """
 from __future__ import annotations
 
@@ -83,14 +92,44 @@ def bspline_stencil(frac, p):
     return w, dw
 
 
+def gaussian_shape(p, sigma):
+    """Shape b (in grid units squared) of the Gaussian window of NFFT cutoff
+    m on its p = 2m + 2 stencil points, for oversampling factor sigma:
+    b = 2 sigma m / ((2 sigma - 1) pi)."""
+    m = p // 2 - 1
+    return 2.0 * sigma * m / ((2.0 * sigma - 1.0) * math.pi)
+
+
+def gaussian_stencil(frac, p, b):
+    """Gaussian window weights exp(-d^2/b) on the same p stencil points as
+    bspline_stencil (l = floor(s) - p/2 + 1 + j, signed distance
+    d = s - l = frac + p/2 - 1 - j, -p/2 < d < p/2: for p = 2m + 2 the
+    points floor(s) - m .. floor(s) + m + 1 of an NFFT of cutoff m), and
+    their derivatives with respect to s, -2 d/b exp(-d^2/b)."""
+    frac = np.asarray(frac, np.float64)
+    d = frac[..., None] + (p // 2 - 1) - np.arange(p)
+    w = np.exp(-d * d / b)
+    return w, -2.0 * d / b * w
+
+
+def kept_modes(M, sigma):
+    """Modes kept per axis under oversampling sigma: K = 2 floor(M/(2 sigma))."""
+    return 2 * int(math.floor(M / (2.0 * sigma) + 1e-9))
+
+
 def window_ft(M, p, kind="continuous"):
     """Fourier coefficients c(n) of the B-spline window along one axis, for
     n in numpy FFT order (0, 1, .., M/2-1, -M/2, .., -1).
 
     continuous: sinc(pi n/M)^p, the Fourier transform of B_p at n/M.
     discrete:   sum_j B_p(j) exp(-2 pi i n j/M) over the integer nodes j.
+    gaussian:   the Gaussian window's transform sqrt(pi b) exp(-b (pi n/M)^2)
+                (pass kind=("gaussian", b)).
     """
     n = np.fft.fftfreq(M, 1.0 / M)
+    if isinstance(kind, tuple) and kind[0] == "gaussian":
+        b = kind[1]
+        return math.sqrt(math.pi * b) * np.exp(-b * (np.pi * n / M) ** 2)
     if kind == "continuous":
         t = np.pi * n / M
         s = np.ones_like(t)
@@ -123,22 +162,26 @@ def grid_coords(x, box, M):
     return s
 
 
-def _stencil(s, M, p):
+def _stencil(s, M, p, gauss_b=None):
     fl = np.floor(s)
     frac = s - fl
     base = fl.astype(np.int64) - p // 2 + 1
     ws, dws, idx = [], [], []
     for d in range(3):
-        w, dw = bspline_stencil(frac[:, d], p)
+        if gauss_b is None:
+            w, dw = bspline_stencil(frac[:, d], p)
+        else:
+            w, dw = gaussian_stencil(frac[:, d], p, gauss_b)
         ws.append(w)
         dws.append(dw)
         idx.append(np.mod(base[:, d][:, None] + np.arange(p)[None, :], M[d]))
     return ws, dws, idx
 
 
-def spread(x, q, box, M, p, chunk=65536):
-    """rho_l = sum_i q_i B_p(s_i - l), periodic (type-1 / transposed step).
-    Grid layout [Mz, My, Mx] (x fastest)."""
+def spread(x, q, box, M, p, chunk=65536, gauss_b=None):
+    """rho_l = sum_i q_i B_p(s_i - l), periodic (type-1 / transposed step);
+    the Gaussian window instead when gauss_b is given.  Grid layout
+    [Mz, My, Mx] (x fastest)."""
     M = np.asarray(M)
     rho = np.zeros(int(np.prod(M)))
     n = len(q)
@@ -149,7 +192,7 @@ def spread(x, q, box, M, p, chunk=65536):
         if not keep.any():
             continue
         s = grid_coords(x[sl][keep], box, M)
-        ws, _, idx = _stencil(s, M, p)
+        ws, _, idx = _stencil(s, M, p, gauss_b)
         wx, wy, wz = ws
         ix, iy, iz = idx
         val = (qq[keep][:, None, None, None] * wz[:, :, None, None] *
@@ -159,7 +202,7 @@ def spread(x, q, box, M, p, chunk=65536):
     return rho.reshape(M[2], M[1], M[0])
 
 
-def interpolate(grids, x, box, M, p, deriv=False, chunk=32768):
+def interpolate(grids, x, box, M, p, deriv=False, chunk=32768, gauss_b=None):
     """Type-2 / conjugated step: for each particle and each grid g,
     sum_l B_p(s_i - l) g_l.  With deriv=True also returns the gradient of
     that sum with respect to the grid coordinate s (shape [N, ngrid, 3])."""
@@ -171,7 +214,7 @@ def interpolate(grids, x, box, M, p, deriv=False, chunk=32768):
     for a in range(0, n, chunk):
         sl = slice(a, min(n, a + chunk))
         s = grid_coords(x[sl], box, M)
-        ws, dws, idx = _stencil(s, M, p)
+        ws, dws, idx = _stencil(s, M, p, gauss_b)
         ix, iy, iz = idx
         lin = (iz[:, :, None, None] * M[1] + iy[:, None, :, None]) * M[0] + ix[:, None, None, :]
         w3 = ws[2][:, :, None, None] * ws[1][:, None, :, None] * ws[0][:, None, None, :]
@@ -191,8 +234,10 @@ def interpolate(grids, x, box, M, p, deriv=False, chunk=32768):
 # --------------------------------------------------------------------------
 # reciprocal space
 # --------------------------------------------------------------------------
-def kgrid(box, M):
-    """k vectors and the mode mask K on the [Mz, My, Mx] FFT layout."""
+def kgrid(box, M, K=None):
+    """k vectors and the mode mask on the [Mz, My, Mx] FFT layout: every
+    mode but the Nyquist index and n = 0, or with K (kept modes per axis)
+    only |n_d| < K_d/2."""
     M = np.asarray(M)
     ns = [np.fft.fftfreq(M[d], 1.0 / M[d]) for d in range(3)]
     nz, ny, nx = np.meshgrid(ns[2], ns[1], ns[0], indexing="ij")
@@ -201,22 +246,30 @@ def kgrid(box, M):
     kz = 2 * np.pi * nz / box[2]
     mask = ((nx != -M[0] // 2) & (ny != -M[1] // 2) & (nz != -M[2] // 2) &
             ~((nx == 0) & (ny == 0) & (nz == 0)))
+    if K is not None:
+        mask &= (2 * np.abs(nx) < K[0]) & (2 * np.abs(ny) < K[1]) & (2 * np.abs(nz) < K[2])
     return (kx, ky, kz), mask
 
 
-def reciprocal(x, q, box, alpha, M, p, ke=1.0, window="continuous", want_grad=True):
+def reciprocal(x, q, box, alpha, M, p, ke=1.0, window="continuous", want_grad=True, sigma=1.0):
     """ENUF k-space part: energy, ik forces, potentials and the exact
-    gradient of the discrete energy, all in FP64."""
+    gradient of the discrete energy, all in FP64.  window="gaussian": the
+    paper's NFFT form with the Gaussian window of shape gaussian_shape(p,
+    sigma); sigma > 1 keeps only the modes |n_d| < K_d/2 (kept_modes) of
+    either window."""
     x = np.asarray(x, np.float64)
     q = np.asarray(q, np.float64)
     box = np.asarray(box, np.float64)
     M = np.asarray(M)
     V = float(np.prod(box))
-    rho = spread(x, q, box, M, p)
+    gb = gaussian_shape(p, sigma) if window == "gaussian" else None
+    rho = spread(x, q, box, M, p, gauss_b=gb)
     rho_hat = np.fft.fftn(rho)                       # exp(-2 pi i n.l/M), unnormalised
-    c = [window_ft(int(M[d]), p, window) for d in range(3)]
+    kind = ("gaussian", gb) if gb is not None else window
+    c = [window_ft(int(M[d]), p, kind) for d in range(3)]
     cfull = c[2][:, None, None] * c[1][None, :, None] * c[0][None, None, :]
-    (kx, ky, kz), mask = kgrid(box, M)
+    K = None if sigma == 1.0 else [kept_modes(int(M[d]), sigma) for d in range(3)]
+    (kx, ky, kz), mask = kgrid(box, M, K)
     k2 = kx * kx + ky * ky + kz * kz
     A = np.zeros_like(k2)
     A[mask] = np.exp(-k2[mask] / (4 * alpha * alpha)) / k2[mask]
@@ -228,7 +281,7 @@ def reciprocal(x, q, box, alpha, M, p, ke=1.0, window="continuous", want_grad=Tr
         gh = -1j * kd * A * S / cfull
         fields.append(np.real(np.fft.ifftn(gh)) * G)
     psi = np.real(np.fft.ifftn(A * S / cfull)) * G
-    vals, dvals = interpolate(fields + [psi], x, box, M, p, deriv=want_grad)
+    vals, dvals = interpolate(fields + [psi], x, box, M, p, deriv=want_grad, gauss_b=gb)
     pref = ke * 4 * np.pi / V
     f_k = pref * q[:, None] * vals[:, :3]
     phi_k = pref * vals[:, 3]
@@ -240,14 +293,14 @@ def reciprocal(x, q, box, alpha, M, p, ke=1.0, window="continuous", want_grad=Tr
     return out
 
 
-def enuf(x, q, box, alpha, rc, M, p, ke=1.0, window="continuous", want_grad=True):
+def enuf(x, q, box, alpha, rc, M, p, ke=1.0, window="continuous", want_grad=True, sigma=1.0):
     """Full ENUF evaluation: real space from the direct oracle (minimum image),
     reciprocal space by the gridding steps above, self and background terms."""
     x = np.asarray(x, np.float64)
     q = np.asarray(q, np.float64)
     box = np.asarray(box, np.float64)
     e_r, f_r, phi_r = _ewald.real_minimage(x, q, box, alpha, rc, ke)
-    rec = reciprocal(x, q, box, alpha, M, p, ke, window, want_grad)
+    rec = reciprocal(x, q, box, alpha, M, p, ke, window, want_grad, sigma)
     e_s, e_b, phi_s, phi_b = _ewald.self_terms(q, box, alpha, ke)
     out = dict(rec)
     out.update({

@@ -186,3 +186,102 @@ def test_single_charge_background():
     m = em.enuf(x, q, box, 6.0 / L, L / 2, (32, 32, 32), 8, want_grad=False)
     expect = -2.837297479480619 / (2 * L)
     assert abs(m["E"] - expect) < 1e-8
+
+
+# ---- the paper's NFFT form: Gaussian window, oversampling ----------------
+def test_gaussian_transform_matches_quadrature():
+    """The scaling step's closed form sqrt(pi b) exp(-b (pi n/M)^2) is the
+    Fourier transform of exp(-d^2/b): checked by numerical quadrature."""
+    from scipy.integrate import quad
+
+    for p, sigma in ((4, 2.0), (6, 1.5), (8, 2.0)):
+        b = em.gaussian_shape(p, sigma)
+        M = 32
+        c = em.window_ft(M, p, ("gaussian", b))
+        for n in (0, 3, 7):
+            val, _ = quad(lambda d: math.exp(-d * d / b) * math.cos(2 * math.pi * n * d / M), -40, 40,
+                          limit=400, epsabs=1e-14)
+            assert abs(val - c[n]) < 1e-10 * max(1.0, abs(val))
+
+
+def test_gaussian_stencil_sum_approaches_its_transform():
+    """Poisson summation for the truncated Gaussian stencil: the stencil's
+    own Fourier sum at a kept mode equals the continuous transform (times
+    the particle's phase) up to the truncation and aliasing error, which
+    falls with the cutoff m at fixed oversampling."""
+    rng = np.random.default_rng(5)
+    M, sigma = 64, 2.0
+    K = em.kept_modes(M, sigma)
+    n = np.arange(-(K // 2) + 1, K // 2)
+    errs = []
+    for p in (4, 6, 8):
+        b = em.gaussian_shape(p, sigma)
+        worst = 0.0
+        for s in rng.uniform(0, M, 20):
+            fl = math.floor(s)
+            w, _ = em.gaussian_stencil(np.array([s - fl]), p, b)
+            ls = fl - p // 2 + 1 + np.arange(p)
+            disc = (w[0][None, :] * np.exp(-2j * np.pi * n[:, None] * ls[None, :] / M)).sum(1)
+            cont = math.sqrt(math.pi * b) * np.exp(-b * (np.pi * n / M) ** 2) * np.exp(-2j * np.pi * n * s / M)
+            worst = max(worst, float(np.abs(disc / cont - 1).max()))
+        errs.append(worst)
+    # (largest at the highest kept mode, where the first alias is nearest)
+    assert errs[0] > 5 * errs[1] > 25 * errs[2]
+    assert errs[2] < 2e-3
+
+
+def test_gaussian_window_derivative_is_finite_difference():
+    t = np.linspace(0.05, 0.95, 9)
+    h = 1e-6
+    b = em.gaussian_shape(6, 2.0)
+    _, dw = em.gaussian_stencil(t, 6, b)
+    wp, _ = em.gaussian_stencil(t + h, 6, b)
+    wm, _ = em.gaussian_stencil(t - h, 6, b)
+    assert np.abs((wp - wm) / (2 * h) - dw).max() < 1e-8
+
+
+def test_kept_modes():
+    assert em.kept_modes(64, 1.0) == 64 and em.kept_modes(64, 2.0) == 32
+    assert em.kept_modes(64, 1.5) == 42 and em.kept_modes(32, 1.5) == 20
+
+
+def _fig1_system():
+    rng = np.random.default_rng(3)
+    n = 400
+    box = np.array([12.0, 12.0, 12.0])
+    x = rng.uniform(0, 1, (n, 3)) * box
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    delta, rc = 1e-5, 6.0
+    return x, q, box, math.sqrt(-math.log(delta)) / rc, rc
+
+
+@pytest.mark.parametrize("sigma", [1.5, 2.0])
+def test_gaussian_energy_error_falls_with_m(sigma):
+    """The energy error of the oversampled Gaussian form against the Ewald
+    sum over the same kept modes falls steeply with the NFFT cutoff m and is
+    at the Ewald accuracy (delta = 1e-5) from m = 2 on."""
+    x, q, box, alpha, rc = _fig1_system()
+    M = 32
+    K = em.kept_modes(M, sigma)
+    ref = ew.ewald(x, q, box, alpha, rc, kset="modes", M=(K, K, K))
+    errs = []
+    for m in (1, 2, 3):
+        r = em.enuf(x, q, box, alpha, rc, (M, M, M), 2 * m + 2, window="gaussian", sigma=sigma, want_grad=False)
+        errs.append(abs(r["E"] - ref["E"]) / abs(ref["E"]))
+    assert errs[0] > 10 * errs[1] > 10 * errs[2] / 2
+    assert errs[1] < 1e-4 and errs[2] < 1e-5
+
+
+def test_gaussian_gradient_is_exact_derivative_of_discrete_energy():
+    x, q, box = _sys()
+    M, p, alpha = (16, 16, 32), 6, 1.1
+    rec = em.reciprocal(x, q, box, alpha, M, p, window="gaussian", sigma=2.0)
+    h = 1e-6
+    for i in (0, 7, 33):
+        for d in range(3):
+            xp = x.copy(); xp[i, d] += h
+            xm = x.copy(); xm[i, d] -= h
+            ep = em.reciprocal(xp, q, box, alpha, M, p, window="gaussian", sigma=2.0, want_grad=False)["E_K"]
+            emi = em.reciprocal(xm, q, box, alpha, M, p, window="gaussian", sigma=2.0, want_grad=False)["E_K"]
+            assert abs((ep - emi) / (2 * h) - rec["grad_K"][i, d]) < 1e-7 * max(1.0, np.abs(rec["grad_K"]).max())
+    assert abs(0.5 * np.dot(q, rec["phi_K"]) - rec["E_K"]) < 1e-12 * abs(rec["E_K"])
