@@ -19,11 +19,13 @@
  *   E_bg   neutralising-background energy -ke pi Q^2 / (2 V alpha^2), zero
  *          for neutral systems (the paper assumes neutrality).
  *
- * Readings fixed by this library: the grid M is the FFT size per axis and all
- * its modes except the Nyquist index -M/2 are kept (no oversampling); the
- * window is the centred cardinal B-spline of order p (p grid points of
- * support per axis) and the scaling step divides by its continuous Fourier
- * transform sinc^p(pi n/M).
+ * Readings fixed by this library: the grid M is the FFT size per axis and,
+ * by default, all its modes except the Nyquist index -M/2 are kept (no
+ * oversampling); the default window is the centred cardinal B-spline of
+ * order p (p grid points of support per axis) and the scaling step divides
+ * by its continuous Fourier transform sinc^p(pi n/M).  The paper's own NFFT
+ * form (Gaussian window, oversampling) is available through
+ * ENUF_OPT_WINDOW and ENUF_OPT_OVERSAMPLING.
  *
  * Conventions for every call:
  *  - Return value: ENUF_OK (0) or an error code; a failed call has no effect
@@ -92,7 +94,7 @@ typedef enum {
                                  energy; their sum is zero only to the
                                  method's accuracy.  One inverse transform
                                  instead of three. */
-    ENUF_OPT_SLATER = 5       /* ENUF-DPD (paper Sec. 2.4, Eq. 51-58): value =
+    ENUF_OPT_SLATER = 5,      /* ENUF-DPD (paper Sec. 2.4, Eq. 51-58): value =
                                  lambda_e > 0, the decay length of Slater-type
                                  smeared charges (beta = R_c / lambda_e); 0
                                  (default): point charges.  Each real-space
@@ -107,6 +109,24 @@ typedef enum {
                                  scaled energy exactly; for the erfc-screened
                                  pair term that differs from the B_F-scaled
                                  force, which follows the paper. */
+    ENUF_OPT_WINDOW = 6,      /* NFFT window (paper Sec. 2.2): 0 (default)
+                                 cardinal B-spline of order p; 1 the
+                                 Gaussian exp(-d^2/b) of the paper's NFFT
+                                 (Sec. 3.1), cutoff m = p/2 - 1 on the same
+                                 p = 2m + 2 stencil points floor(s) - m ..
+                                 floor(s) + m + 1, shape
+                                 b = 2 sigma m / ((2 sigma - 1) pi), scaling
+                                 by its transform sqrt(pi b) exp(-b (pi n/M)^2);
+                                 needs p >= 4. */
+    ENUF_OPT_OVERSAMPLING = 7 /* oversampling factor sigma >= 1 (Sec. 2.2,
+                                 2.3.2): of the M_d-point grid only the modes
+                                 |n_d| < K_d/2, K_d = 2 floor(M_d/(2 sigma)),
+                                 enter the k-space sums (default 1: every
+                                 mode but the Nyquist index).  Setting either
+                                 option re-initialises the workspace tables
+                                 on the stream and forgets the last
+                                 evaluation (a following enuf_energy_grad
+                                 reports ENUF_ESTATE). */
 } enuf_option;
 
 /* Internal buffers enuf_stage_copy() can read (for tests of single steps). */

@@ -40,6 +40,8 @@ struct GraphCache {
   void *F = nullptr, *phi = nullptr, *ws = nullptr;
   bool analytic = false;
   double ke = 0.0, slater = 0.0;
+  int win = 0;
+  double sigma = 1.0;
 };
 
 constexpr size_t kScratchBytes = ENUF_NOALLOC_SCRATCH_BYTES;
@@ -171,6 +173,12 @@ static void release(enuf_ctx c) {
   c->gst = nullptr;
 }
 
+// Window and kept modes from the options: kept_d = 2 floor(M_d / (2 sigma)),
+// and for the Gaussian the NFFT shape b = 2 sigma m / ((2 sigma - 1) pi) of
+// cutoff m = p/2 - 1.  The tables depend on them: a context with a workspace
+// initialises it again (which also forgets the last evaluation).
+static enuf_status apply_window(enuf_ctx c, int win, double sigma);
+
 static hipError_t sync_stream(enuf_ctx c) { return c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize(); }
 
 // Point the context at a workspace block (aligned up) and enqueue its
@@ -204,7 +212,8 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
                             bool an) {
   GraphCache &gc = c->gc;
   const bool hit = gc.exec && gc.x == x && gc.q == q && gc.E == E && gc.F == F && gc.phi == phi &&
-                   gc.ws == c->w.grid && gc.analytic == an && gc.ke == c->g.ke && gc.slater == c->g.slater;
+                   gc.ws == c->w.grid && gc.analytic == an && gc.ke == c->g.ke && gc.slater == c->g.slater &&
+                   gc.win == c->g.win && gc.sigma == c->g.sigma;
   if (!hit) {
     drop_graph(c);
     hipGraph_t graph = nullptr;
@@ -231,6 +240,8 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
     gc.analytic = an;
     gc.ke = c->g.ke;
     gc.slater = c->g.slater;
+    gc.win = c->g.win;
+    gc.sigma = c->g.sigma;
   }
   hipError_t e = hipEventRecord(c->gev[0], c->st);
   if (e == hipSuccess) e = hipStreamWaitEvent(c->gst, c->gev[0], 0);
@@ -311,6 +322,10 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   g.rc = r_c;
   g.ke = 1.0;
   g.slater = 0.0;
+  g.win = 0;
+  g.gb = g.gib = 0.0;
+  g.sigma = 1.0;
+  for (int d = 0; d < 3; ++d) g.kept[d] = g.M[d];
 
   const size_t rs = precision == ENUF_FP64 ? 8 : 4;
   if (!enuf::fft_plans_fit(g, precision == ENUF_FP64))
@@ -445,8 +460,41 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       if (!(value >= 0.0) || !std::isfinite(value)) return fail(ctx, ENUF_EINVAL, "lambda_e must be >= 0 and finite");
       ctx->g.slater = value;
       return ENUF_OK;
+    case ENUF_OPT_WINDOW:
+      if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "window is 0 (B-spline) or 1 (Gaussian)");
+      if (value == 1.0 && ctx->g.p < 4) return fail(ctx, ENUF_EINVAL, "the Gaussian window needs p >= 4 (cutoff m = p/2 - 1 >= 1)");
+      return apply_window(ctx, (int)value, ctx->g.sigma);
+    case ENUF_OPT_OVERSAMPLING:
+      if (!(value >= 1.0) || !std::isfinite(value)) return fail(ctx, ENUF_EINVAL, "oversampling factor must be >= 1");
+      for (int d = 0; d < 3; ++d)
+        if (2 * (int)std::floor(ctx->g.M[d] / (2.0 * value) + 1e-9) < 2)
+          return fail(ctx, ENUF_EINVAL, "oversampling leaves no mode on some axis");
+      return apply_window(ctx, ctx->g.win, value);
   }
   return fail(ctx, ENUF_EINVAL, "unknown option");
+}
+
+static enuf_status apply_window(enuf_ctx c, int win, double sigma) {
+  Geom &g = c->g;
+  g.win = win;
+  g.sigma = sigma;
+  for (int d = 0; d < 3; ++d) g.kept[d] = 2 * (int)std::floor(g.M[d] / (2.0 * sigma) + 1e-9);
+  if (win == 1) {
+    const int m = g.p / 2 - 1;
+    g.gb = 2.0 * sigma * m / ((2.0 * sigma - 1.0) * 3.14159265358979323846);
+    g.gib = 1.0 / g.gb;
+  } else {
+    g.gb = g.gib = 0.0;
+  }
+  drop_graph(c);
+  if (!c->have_ws) return ENUF_OK;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  c->w.nruns = c->nruns;
+  e = enuf::launch_init_ws(g, c->w, c->st, c->prec == ENUF_FP64);
+  if (e != hipSuccess) return hip_fail(c, e, "workspace initialisation");
+  c->have_forward = false;
+  return ENUF_OK;
 }
 
 enuf_status enuf_set_stream(enuf_ctx ctx, void *stream) {

@@ -48,6 +48,12 @@ struct Geom {
   double cL[3];
   double alpha, rc, ke;
   double slater;   // ENUF-DPD decay length lambda_e of smeared charges (0: point charges)
+  // window: 0 cardinal B-spline of order p; 1 Gaussian exp(-d^2/gb) of NFFT
+  // cutoff m = p/2 - 1 (gib = 1/gb, in grid units)
+  int win;
+  double gb, gib;
+  double sigma;    // oversampling factor: modes |n_d| < kept[d]/2 are kept
+  int kept[3];
 };
 
 // Two-level counting sort layout: particles are counted in `nblk` blocks of

@@ -208,6 +208,44 @@ __device__ __forceinline__ void bspline_d(R f, R (&w)[P], R (&dw)[P]) {
   }
 }
 
+__device__ __forceinline__ float exp_win(float v) { return __expf(v); }
+__device__ __forceinline__ double exp_win(double v) { return exp(v); }
+
+// The window the context uses on a particle's P stencil points (the same
+// points for both windows: floor(s) - P/2 + 1 + j): the cardinal B-spline
+// above, or the Gaussian exp(-d^2/b) of the paper's NFFT form, d = s - l =
+// f + P/2 - 1 - j (for P = 2m + 2 the points floor(s) - m .. floor(s) + m + 1
+// of an NFFT of cutoff m).  The branch is uniform across a launch.
+template <typename R, int P>
+__device__ __forceinline__ void window_w(R f, R (&w)[P], const Geom &g) {
+  if (g.win == 0) {
+    bspline<R, P>(f, w);
+    return;
+  }
+  const R ib = (R)g.gib;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const R d = f + R(P / 2 - 1 - j);
+    w[j] = exp_win(-d * d * ib);
+  }
+}
+
+// Weights and their derivatives with respect to s.
+template <typename R, int P>
+__device__ __forceinline__ void window_wd(R f, R (&w)[P], R (&dw)[P], const Geom &g) {
+  if (g.win == 0) {
+    bspline_d<R, P>(f, w, dw);
+    return;
+  }
+  const R ib = (R)g.gib;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const R d = f + R(P / 2 - 1 - j);
+    w[j] = exp_win(-d * d * ib);
+    dw[j] = R(-2) * d * ib * w[j];
+  }
+}
+
 // --------------------------------------------------------------------------
 // fills
 // --------------------------------------------------------------------------
@@ -837,7 +875,7 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
         R w[P];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          bspline<R, P>(fr[d], w);
+          window_w<R, P>(fr[d], w, g);
           const R sc = (d == aC) ? v.w : R(1);
           R *dst = (d == aA) ? wA[slot] : ((d == aB) ? wB[slot] : wC[slot]);
 #pragma unroll
@@ -1026,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         float w[P];
-        bspline<float, P>(fr[d], w);
+        window_w<float, P>(fr[d], w, g);
         const float sc = d == 2 ? qv : 1.0f;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -1645,13 +1683,13 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
     R wy[P], wz[P], dy[P], dz[P];
     R fl = floor(s[0]);
     b[0] = (int)fl - P / 2 + 1;
-    if (GRAD) bspline_d<R, P>(s[0] - fl, wx, dx); else bspline<R, P>(s[0] - fl, wx);
+    if (GRAD) window_wd<R, P>(s[0] - fl, wx, dx, g); else window_w<R, P>(s[0] - fl, wx, g);
     fl = floor(s[1]);
     b[1] = (int)fl - P / 2 + 1;
-    if (GRAD) bspline_d<R, P>(s[1] - fl, wy, dy); else bspline<R, P>(s[1] - fl, wy);
+    if (GRAD) window_wd<R, P>(s[1] - fl, wy, dy, g); else window_w<R, P>(s[1] - fl, wy, g);
     fl = floor(s[2]);
     b[2] = (int)fl - P / 2 + 1;
-    if (GRAD) bspline_d<R, P>(s[2] - fl, wz, dz); else bspline<R, P>(s[2] - fl, wz);
+    if (GRAD) window_wd<R, P>(s[2] - fl, wz, dz, g); else window_w<R, P>(s[2] - fl, wz, g);
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       ws[0][k] = wy[k];
@@ -1835,13 +1873,13 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
     {
       R fl = floor(v.x);
       l[0] = (int)fl - t0[0];
-      if (GRAD) bspline_d<R, P>(v.x - fl, wx, dx); else bspline<R, P>(v.x - fl, wx);
+      if (GRAD) window_wd<R, P>(v.x - fl, wx, dx, g); else window_w<R, P>(v.x - fl, wx, g);
       fl = floor(v.y);
       l[1] = (int)fl - t0[1];
-      if (GRAD) bspline_d<R, P>(v.y - fl, wy, dy); else bspline<R, P>(v.y - fl, wy);
+      if (GRAD) window_wd<R, P>(v.y - fl, wy, dy, g); else window_w<R, P>(v.y - fl, wy, g);
       fl = floor(v.z);
       l[2] = (int)fl - t0[2];
-      if (GRAD) bspline_d<R, P>(v.z - fl, wz, dz); else bspline<R, P>(v.z - fl, wz);
+      if (GRAD) window_wd<R, P>(v.z - fl, wz, dz, g); else window_w<R, P>(v.z - fl, wz, g);
     }
     R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
     // this lane's (z, y) rows: with four lanes z = za + 2m, y = yb + 2n (za,
@@ -2480,8 +2518,10 @@ size_t table_size(const Geom &g, size_t off[kTabSlots]) {
 // by kernels alone (no host copy): every table entry in FP64, cast to the
 // precision.  Twiddles e^{-2 pi i m / period}; per axis the influence factor
 // s_d = exp(-k_d^2 / 4 alpha^2) / c_d^2 with the window transform
-// c_d = sinc^p(pi n / M_d) (n signed; zero at the Nyquist index, which is
-// outside the k-set) and the wave number k_d = 2 pi n / L_d.  Thread 0 also
+// c_d = sinc^p(pi n / M_d) of the B-spline, or sqrt(pi b) exp(-b (pi n/M_d)^2)
+// of the Gaussian (n signed; zero at the Nyquist index and, when
+// oversampling, at |n| >= kept_d / 2: both outside the k-set), and the wave
+// number k_d = 2 pi n / L_d.  Thread 0 also
 // writes the spread run table and clears the flags; block 0 clears the
 // energy slots.
 struct TabOff {
@@ -2509,12 +2549,17 @@ __global__ __launch_bounds__(256) void k_init_ws(Geom g, TabOff t, R *__restrict
       const double kd = 2.0 * pi * (double)nn / g.L[d];
       if (seg >= 7) {
         v = kd;
-      } else if (k == M / 2) {
-        v = 0.0;
+      } else if (k == M / 2 || 2 * (nn < 0 ? -nn : nn) >= g.kept[d]) {
+        v = 0.0;  // the Nyquist index, and modes beyond the kept set when oversampling
       } else {
-        const double r = nn == 0 ? 1.0 : sinpi((double)nn / (double)M) / (pi * (double)nn / (double)M);
         double c = 1.0;
-        for (int j = 0; j < g.p; ++j) c *= r;
+        if (g.win == 0) {
+          const double r = nn == 0 ? 1.0 : sinpi((double)nn / (double)M) / (pi * (double)nn / (double)M);
+          for (int j = 0; j < g.p; ++j) c *= r;
+        } else {
+          const double t = pi * (double)nn / (double)M;
+          c = sqrt(pi * g.gb) * exp(-g.gb * t * t);
+        }
         v = exp(-kd * kd / (4.0 * g.alpha * g.alpha)) / (c * c);
       }
     }

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libenuf.so")
 
 ENUF_OK, ENUF_EINVAL, ENUF_ENOMEM, ENUF_EDEVICE, ENUF_ENONFINITE, ENUF_ESTATE, ENUF_EUNSUPPORTED = range(7)
 ENUF_FP64, ENUF_FP32 = 0, 1
-OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE, OPT_SLATER = 0, 1, 2, 3, 4, 5
+OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE, OPT_SLATER, OPT_WINDOW, OPT_OVERSAMPLING = range(8)
+WINDOWS = {"bspline": 0, "gaussian": 1}
 FORCE_MODES = {"ik": 0, "analytic": 1}
 STAGE_GRID, STAGE_SPECTRUM, STAGE_FIELDS, STAGE_SORTED, STAGE_COUNTS, STAGE_CELLS = range(6)
 PHASES = ("prep", "sort", "spread", "fft_fwd", "influence_z", "fft_inv", "gather", "pair", "finalize")
@@ -103,10 +104,13 @@ class Enuf:
     """
 
     def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False,
-                 force_mode="ik", slater=None, workspace=True):
+                 force_mode="ik", slater=None, workspace=True, window="bspline", oversampling=1.0):
         """slater: decay length lambda_e of ENUF-DPD Slater-type smeared
         charges (paper Sec. 2.4); None for point charges.  workspace: give
-        the context a workspace held in a torch uint8 tensor (False: none)."""
+        the context a workspace held in a torch uint8 tensor (False: none).
+        window ("bspline" or "gaussian", the paper's NFFT window of cutoff
+        m = p/2 - 1) and oversampling (sigma >= 1: only the modes |n_d| <
+        K_d/2, K_d = 2 floor(M_d / 2 sigma), are kept)."""
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("ENUF needs a HIP GPU; torch.cuda.is_available() is False")
@@ -149,6 +153,11 @@ class Enuf:
         self.slater = slater
         if slater is not None:
             self.set_option(OPT_SLATER, float(slater))
+        self.window, self.oversampling = window, float(oversampling)
+        if window != "bspline":
+            self.set_option(OPT_WINDOW, WINDOWS[window])
+        if oversampling != 1.0:
+            self.set_option(OPT_OVERSAMPLING, float(oversampling))
         self._E = torch.zeros(5, dtype=torch.float64, device=self.device)
 
     # -- plumbing ---------------------------------------------------------
