@@ -118,7 +118,7 @@ typedef enum {
                                  b = 2 sigma m / ((2 sigma - 1) pi), scaling
                                  by its transform sqrt(pi b) exp(-b (pi n/M)^2);
                                  needs p >= 4. */
-    ENUF_OPT_OVERSAMPLING = 7 /* oversampling factor sigma >= 1 (Sec. 2.2,
+    ENUF_OPT_OVERSAMPLING = 7,/* oversampling factor sigma >= 1 (Sec. 2.2,
                                  2.3.2): of the M_d-point grid only the modes
                                  |n_d| < K_d/2, K_d = 2 floor(M_d/(2 sigma)),
                                  enter the k-space sums (default 1: every
@@ -127,6 +127,27 @@ typedef enum {
                                  on the stream and forgets the last
                                  evaluation (a following enuf_energy_grad
                                  reports ENUF_ESTATE). */
+    ENUF_OPT_SKIN = 8         /* persistent binning for MD (skin length
+                                 >= 0; default 0: every evaluation sorts).
+                                 With skin s > 0 the particle orders of the
+                                 last sort are kept while no particle has
+                                 moved more than s/2 (minimum image) since
+                                 it, every charge is unchanged and the phi
+                                 request matches; the check runs on the
+                                 device (no host synchronisation) and an
+                                 evaluation that keeps the orders only
+                                 refreshes the sorted positions.  Real-space
+                                 cells then have side > r_c + s, the spread's
+                                 tile classes a margin of ceil(s/2 M/L) grid
+                                 points (ENUF_EUNSUPPORTED when p plus twice
+                                 that exceeds the spread tile plus one), and
+                                 the interpolation reads the grid per
+                                 particle.  Results equal those of a sorting
+                                 evaluation up to summation order.  The
+                                 cell geometry changes, so a context with a
+                                 workspace lays it out again (ENUF_ESTATE if
+                                 it is too small) and forgets the last
+                                 evaluation. */
 } enuf_option;
 
 /* Internal buffers enuf_stage_copy() can read (for tests of single steps). */
@@ -142,7 +163,10 @@ typedef enum {
                                  real [Mz][My][Mx] */
     ENUF_STAGE_SORTED = 3,    /* int32 [N] permutation, grid-tile order
                                  (entries past the active count are unused) */
-    ENUF_STAGE_COUNTS = 4,    /* int32 [2]: active particles, charged particles */
+    ENUF_STAGE_COUNTS = 4,    /* int32 [8]: active particles, charged particles,
+                                 non-finite flag, (internal), (internal),
+                                 sorts performed since the workspace was
+                                 set, (spare), (spare) */
     ENUF_STAGE_CELLS = 5      /* int32 [N] permutation, pair-cell order */
 } enuf_stage;
 

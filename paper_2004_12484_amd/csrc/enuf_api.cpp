@@ -74,6 +74,8 @@ struct enuf_ctx_s {
   int device = 0;
   bool have_ws = false;
   void *owned_ws = nullptr;    // workspace from enuf_alloc_workspace
+  void *ws = nullptr;          // the workspace block given (before alignment)
+  size_t ws_bytes = 0;
   // the last evaluation on the context workspace, read by the adjoint
   bool have_forward = false;
   bool last_all_active = false;
@@ -106,6 +108,29 @@ static enuf_status hip_fail(enuf_ctx c, hipError_t e, const char *what) {
 }
 
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Real-space cells of side > r_c + skin (at most 2^22 of them) and the spill
+// margin of the tile classes, ceil(skin/2 in grid points) per axis, for
+// persistent binning with that skin (0: none).
+static void set_cells(Geom &g, double skin) {
+  const double side = g.rc + skin;
+  for (int d = 0; d < 3; ++d) {
+    int nc = (int)std::floor(g.L[d] / (side * (1.0 + 1e-5)));
+    g.nc[d] = std::max(1, std::min(nc, 1024));
+  }
+  while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > (int64_t(1) << 22)) {
+    int dm = 0;
+    for (int d = 1; d < 3; ++d) if (g.nc[d] > g.nc[dm]) dm = d;
+    g.nc[dm] = std::max(1, g.nc[dm] / 2);
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.cL[d] = g.nc[d] / g.L[d];
+    g.sdig[d] = skin > 0.0 ? (int)std::ceil(0.5 * skin * g.mL[d] - 1e-12) : 0;
+    if (skin > 0.0) g.sdig[d] = std::max(1, g.sdig[d]);
+  }
+  g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
+  g.skin = skin;
+}
 
 static size_t real_bytes(enuf_ctx c) { return c->prec == ENUF_FP64 ? 8 : 4; }
 
@@ -140,7 +165,10 @@ static size_t layout(const Geom &g, size_t rs, char *base, Work *w) {
   t.ik_t = (int2 *)take(n * sizeof(int2));
   t.ik_c = (int2 *)take(n * sizeof(int2));
   t.runs = (int *)take((size_t)5 * enuf::kMaxRuns * 4);
-  t.counts = (int *)take(4 * 4);
+  t.counts = (int *)take(8 * 4);
+  t.x_ref = take(n * 3 * rs);
+  t.q_ref = take(n * rs);
+  t.act = (int *)take(n * 4);
   t.scal = (double *)take(4 * 8);
   t.qpart = (double *)take((size_t)4 * sp.nblk * 8);
   t.eslot = (double *)take((size_t)2 * enuf::kESlots * 8);
@@ -301,25 +329,15 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
     g.T[d] = std::min(tdef[d], M[d] / 2);
     g.nt[d] = M[d] / g.T[d];
     g.L[d] = box[d];
-    int nc = (int)std::floor(box[d] / (r_c * (1.0 + 1e-5)));
-    g.nc[d] = std::max(1, std::min(nc, 1024));
-  }
-  while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > (int64_t(1) << 22)) {
-    int dm = 0;
-    for (int d = 1; d < 3; ++d) if (g.nc[d] > g.nc[dm]) dm = d;
-    g.nc[dm] = std::max(1, g.nc[dm] / 2);
-  }
-  for (int d = 0; d < 3; ++d) {
     g.iL[d] = 1.0 / g.L[d];
     g.mL[d] = g.M[d] / g.L[d];
-    g.cL[d] = g.nc[d] / g.L[d];
   }
   g.ntiles = g.nt[0] * g.nt[1] * g.nt[2];
-  g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
   g.p = p;
   g.n = (int)n;
   g.alpha = alpha;
   g.rc = r_c;
+  set_cells(g, 0.0);
   g.ke = 1.0;
   g.slater = 0.0;
   g.win = 0;
@@ -376,6 +394,8 @@ enuf_status enuf_set_workspace(enuf_ctx ctx, void *ws, size_t bytes) {
   }
   drop_graph(ctx);
   ctx->have_ws = false;
+  ctx->ws = ws;
+  ctx->ws_bytes = bytes;
   return attach(ctx, ws);
 }
 
@@ -460,6 +480,32 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       if (!(value >= 0.0) || !std::isfinite(value)) return fail(ctx, ENUF_EINVAL, "lambda_e must be >= 0 and finite");
       ctx->g.slater = value;
       return ENUF_OK;
+    case ENUF_OPT_SKIN: {
+      if (!(value >= 0.0) || !std::isfinite(value)) return fail(ctx, ENUF_EINVAL, "skin must be >= 0 and finite");
+      Geom g2 = ctx->g;
+      set_cells(g2, value);
+      for (int d = 0; d < 3; ++d)
+        if (g2.p + 2 * g2.sdig[d] > g2.T[d] + 1)
+          return fail(ctx, ENUF_EUNSUPPORTED,
+                      "skin too large for the window and grid: p + 2 ceil(skin/2 M/L) must not exceed the spread "
+                      "tile (" + std::to_string(g2.T[d]) + " points on axis " + std::to_string(d) + ") plus 1");
+      const size_t rs = real_bytes(ctx);
+      const enuf::SortPlan sp = enuf::sort_plan(g2, (int)rs);
+      const size_t nbk = (size_t)sp.nb[0] + sp.nb[1];
+      if (nbk * sizeof(int) > 65536 || enuf::sort_stage_lds(sp, (int)rs) > 65536 || enuf::sort_fine_lds(sp) > 65536)
+        return fail(ctx, ENUF_EUNSUPPORTED, "too many sort buckets for one workgroup's LDS");
+      if (ctx->have_ws && layout(g2, rs, nullptr, nullptr) > ctx->ws_bytes)
+        return fail(ctx, ENUF_ESTATE, "the workspace is too small for this skin: set a new one of "
+                                      "enuf_workspace_bytes() bytes");
+      ctx->g = g2;
+      drop_graph(ctx);
+      if (ctx->have_ws) {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+        return attach(ctx, ctx->ws);
+      }
+      return ENUF_OK;
+    }
     case ENUF_OPT_WINDOW:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "window is 0 (B-spline) or 1 (Gaussian)");
       if (value == 1.0 && ctx->g.p < 4) return fail(ctx, ENUF_EINVAL, "the Gaussian window needs p >= 4 (cutoff m = p/2 - 1 >= 1)");
@@ -637,7 +683,7 @@ enuf_status enuf_stage_bytes(enuf_ctx ctx, int32_t stage, size_t *bytes) {
     case ENUF_STAGE_SPECTRUM: *bytes = G / 2 * 2 * rs; return ENUF_OK;
     case ENUF_STAGE_FIELDS: *bytes = G * (ctx->last_analytic ? 1 : 4) * rs; return ENUF_OK;
     case ENUF_STAGE_SORTED: *bytes = (size_t)ctx->g.n * 4; return ENUF_OK;
-    case ENUF_STAGE_COUNTS: *bytes = 2 * 4; return ENUF_OK;
+    case ENUF_STAGE_COUNTS: *bytes = 8 * 4; return ENUF_OK;
     case ENUF_STAGE_CELLS: *bytes = (size_t)ctx->g.n * 4; return ENUF_OK;
   }
   return fail(ctx, ENUF_EINVAL, "unknown stage");

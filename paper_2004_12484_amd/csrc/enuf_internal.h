@@ -54,6 +54,11 @@ struct Geom {
   double gb, gib;
   double sigma;    // oversampling factor: modes |n_d| < kept[d]/2 are kept
   int kept[3];
+  // persistent binning (skin > 0): the sorted orders are kept while no
+  // particle has moved more than skin/2; cells have side >= r_c + skin and the
+  // tile spill classes a margin of sdig[d] grid points
+  double skin;
+  int sdig[3];
 };
 
 // Two-level counting sort layout: particles are counted in `nblk` blocks of
@@ -90,7 +95,11 @@ struct Work {
   int2 *ik_c = nullptr;
   int *runs = nullptr;      // [5*nruns] spread neighbour runs (dx, dy, dz, class lo, class hi)
   int nruns = 0;
-  int *counts = nullptr;    // [4]: active, charged, flags, spare
+  int *counts = nullptr;    // [8]: active, charged, flags, sort needed (persistent binning), all-active
+                            // flag of the last sort, sorts performed, spare, spare
+  void *x_ref = nullptr;    // real [n*3] positions at the last sort (persistent binning)
+  void *q_ref = nullptr;    // real [n] charges at the last sort
+  int *act = nullptr;       // [n] 1 for particles active at the last sort
   double *scal = nullptr;   // [4]: Q, Q2, max abs(q), spare
   double *qpart = nullptr;  // [4*nblk] per counting block: sum q, sum q^2, max abs(q), charged count
   double *eslot = nullptr;  // [2*kESlots] energy sums: reciprocal, then real space

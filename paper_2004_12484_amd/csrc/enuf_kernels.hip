@@ -301,9 +301,12 @@ __device__ int block_exscan_int(int v, int *total) {
 // one bucket per workgroup by its fine key in LDS and writes the final order
 // and the bin offsets.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int spill_digit(int local, int T, int P) {
-  if (local < P / 2 - 1) return 0;
-  if (local > T - 1 - P / 2) return 2;
+// D: margin in grid points for particles that may move (persistent binning):
+// the digit then says whether the stencil can cross a face after moving D
+// points (P + 2D <= T + 1 keeps the two faces exclusive).
+__device__ __forceinline__ int spill_digit(int local, int T, int P, int D) {
+  if (local < P / 2 - 1 + D) return 0;
+  if (local > T - 1 - P / 2 - D) return 2;
   return 1;
 }
 
@@ -326,7 +329,7 @@ __device__ __forceinline__ void particle_keys(const R (&xw)[3], const R (&sg)[3]
   for (int d = 0; d < 3; ++d) {
     const int gi = (int)sg[d];
     tix[d] = gi / g.T[d];
-    dig[d] = spill_digit(gi - tix[d] * g.T[d], g.T[d], g.p);
+    dig[d] = spill_digit(gi - tix[d] * g.T[d], g.T[d], g.p, g.sdig[d]);
     const int ci = (int)(xw[d] * R(g.cL[d]));
     cix[d] = ci < g.nc[d] ? ci : g.nc[d] - 1;
   }
@@ -343,7 +346,12 @@ template <typename R>
 __global__ __launch_bounds__(kSortBlock) void k_sort_count(const R *__restrict__ x, const R *__restrict__ q, Geom g,
                                                            SortPlan sp, int all_active, int *__restrict__ key_t,
                                                            int *__restrict__ key_c, int *__restrict__ hist,
-                                                           R *F, R *phi, double *qpart, int *counts) {
+                                                           R *F, R *phi, double *qpart, int *counts, int persist,
+                                                           R *__restrict__ x_ref, R *__restrict__ q_ref,
+                                                           int *__restrict__ act) {
+  // persistent binning: this evaluation keeps the last sort (k_refresh runs)
+  if (persist && counts[3] == 0) return;
+  if (persist && blockIdx.x == 0 && threadIdx.x == 0) counts[4] = all_active;
   extern __shared__ int cnt[];
   const int nbk = sp.nb[0] + sp.nb[1];
   for (int b = threadIdx.x; b < nbk; b += blockDim.x) cnt[b] = 0;
@@ -374,6 +382,13 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const R *__restrict__
       const bool fin = isfinite(p3[0]) && isfinite(p3[1]) && isfinite(p3[2]) && isfinite(qi);
       if (!fin) atomicOr(&counts[2], 1);
       const bool active = fin && (qi != R(0) || all_active);
+      if (persist) {
+        x_ref[3 * i] = p3[0];
+        x_ref[3 * i + 1] = p3[1];
+        x_ref[3 * i + 2] = p3[2];
+        q_ref[i] = qi;
+        act[i] = active ? 1 : 0;
+      }
       if (fin) {
         qs += (double)qi;
         q2 += (double)qi * (double)qi;
@@ -412,6 +427,110 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const R *__restrict__
   }
 }
 
+// Persistent binning, step 1: does this evaluation sort?  counts[3] is 1
+// after a workspace initialisation; otherwise it is set here when some
+// particle has moved more than skin/2 (minimum image) since the last sort, a
+// charge differs from its value then, an input is not finite, or the
+// all-active flag differs.  k_finalize clears it at the end of each
+// evaluation.
+template <typename R>
+__global__ __launch_bounds__(kSortBlock) void k_persist_check(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+                                                              const R *__restrict__ x_ref,
+                                                              const R *__restrict__ q_ref, int all_active,
+                                                              int *counts) {
+  const R lim2 = (R)(0.25 * g.skin * g.skin);
+  const R L0 = (R)g.L[0], L1 = (R)g.L[1], L2 = (R)g.L[2];
+  const R i0 = (R)g.iL[0], i1 = (R)g.iL[1], i2 = (R)g.iL[2];
+  bool bad = blockIdx.x == 0 && threadIdx.x == 0 && counts[4] != all_active;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += gridDim.x * blockDim.x) {
+    const R px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2], qi = q[i];
+    R dx = px - x_ref[3 * i], dy = py - x_ref[3 * i + 1], dz = pz - x_ref[3 * i + 2];
+    dx -= L0 * rint(dx * i0);
+    dy -= L1 * rint(dy * i1);
+    dz -= L2 * rint(dz * i2);
+    const R d2 = dx * dx + dy * dy + dz * dz;
+    // written so that NaN anywhere reads as a violation
+    const bool ok = d2 <= lim2 && qi == q_ref[i] && isfinite(px) && isfinite(py) && isfinite(pz);
+    bad = bad || !ok;
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&counts[3], 1);
+}
+
+// Persistent binning, step 2 (when no sort is needed): the sorted copies of
+// the particles in the kept order, from the current positions and charges:
+// grid coordinates of the wrapped position for the tile order; for the cell
+// order, the position at the last sort (wrapped as the sort wrapped it) plus
+// the minimum-image displacement since, so every particle stays beside the
+// cell it is binned in.  Also the per-block charge sums of k_sort_count and
+// zero outputs for inactive particles.
+template <typename R>
+__global__ __launch_bounds__(kSortBlock) void k_refresh(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+                                                        SortPlan sp, const R *__restrict__ x_ref,
+                                                        const int *__restrict__ act, const int *__restrict__ perm_t,
+                                                        const int *__restrict__ perm_c, real4<R> *__restrict__ part_t,
+                                                        real4<R> *__restrict__ part_c, R *F, R *phi, double *qpart,
+                                                        const int *counts) {
+  if (counts[3] != 0) return;
+  const long long i0 = (long long)blockIdx.x * sp.per;
+  const int i1 = (int)min((long long)g.n, i0 + sp.per);
+  double qs = 0.0, q2 = 0.0, qa = 0.0, nq = 0.0;
+  for (int i = (int)i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const R qi = q[i];
+    qs += (double)qi;
+    q2 += (double)qi * (double)qi;
+    qa = fmax(qa, fabs((double)qi));
+    if (act[i]) {
+      if (qi != R(0)) nq += 1.0;
+    } else {
+      if (F) { F[3 * i] = R(0); F[3 * i + 1] = R(0); F[3 * i + 2] = R(0); }
+      if (phi) phi[i] = R(0);
+    }
+  }
+  const int na = counts[0];
+  for (int k = (int)i0 + threadIdx.x; k < min(i1, na); k += blockDim.x) {
+    {
+      const int i = perm_t[k];
+      const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+      R xw[3], sg[3];
+      particle_coords(p3, g, xw, sg);
+      real4<R> a;
+      a.x = sg[0];
+      a.y = sg[1];
+      a.z = sg[2];
+      a.w = q[i];
+      part_t[k] = a;
+    }
+    {
+      const int i = perm_c[k];
+      const R r3[3] = {x_ref[3 * i], x_ref[3 * i + 1], x_ref[3 * i + 2]};
+      R xw[3], sg[3];
+      particle_coords(r3, g, xw, sg);
+      real4<R> a;
+      R d[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        d[e] = x[3 * i + e] - r3[e];
+        d[e] -= R(g.L[e]) * rint(d[e] * R(g.iL[e]));
+      }
+      a.x = xw[0] + d[0];
+      a.y = xw[1] + d[1];
+      a.z = xw[2] + d[2];
+      a.w = q[i];
+      part_c[k] = a;
+    }
+  }
+  const double a = block_sum(qs);
+  const double b2 = block_sum(q2);
+  const double m = block_max(qa);
+  const double c = block_sum(nq);
+  if (threadIdx.x == 0) {
+    qpart[4 * blockIdx.x] = a;
+    qpart[4 * blockIdx.x + 1] = b2;
+    qpart[4 * blockIdx.x + 2] = m;
+    qpart[4 * blockIdx.x + 3] = c;
+  }
+}
+
 // Exclusive scan over the blocks of each bucket column of hist (in place);
 // the column total goes to the bucket's slot of bbase.  16 columns per
 // workgroup (64-byte row segments), 64 row groups of up to a few rows each,
@@ -421,7 +540,8 @@ __device__ __forceinline__ int bucket_slot(const SortPlan &sp, int b) { return b
 constexpr int kColW = 16, kColG = 64, kColR = 16;  // columns, row groups, rows per group held
 
 __global__ __launch_bounds__(kColW * kColG) void k_sort_colscan(int *__restrict__ hist, SortPlan sp,
-                                                                int *__restrict__ bbase) {
+                                                                int *__restrict__ bbase, const int *need) {
+  if (need && *need == 0) return;
   __shared__ int part[kColG][kColW];
   const int nbk = sp.nb[0] + sp.nb[1];
   const int lane = threadIdx.x % kColW, rg = threadIdx.x / kColW;
@@ -454,7 +574,10 @@ __global__ __launch_bounds__(kColW * kColG) void k_sort_colscan(int *__restrict_
 // and charged counts and the charge sums.
 __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, SortPlan sp, int *off_t, int *off_c,
                                                     const double *__restrict__ qpart, double *scal, int *counts,
-                                                    double *eslot) {
+                                                    double *eslot, int persist) {
+  // with persistent binning an evaluation that keeps the last sort only
+  // reduces the charge sums (from k_refresh's partials)
+  const bool sorting = !persist || counts[3] != 0;
   // the energy slots the transform and pair kernels add into
   for (int i = threadIdx.x; i < 2 * kESlots; i += blockDim.x) eslot[i] = 0.0;
   // per-block charge sums, loaded first so their latency overlaps the scans
@@ -466,7 +589,7 @@ __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, Sor
     c += qpart[4 * i + 3];
   }
   __shared__ int carry;
-  for (int seg = 0; seg < 2; ++seg) {
+  for (int seg = 0; seg < (sorting ? 2 : 0); ++seg) {
     const int lo = seg == 0 ? 0 : sp.nb[0] + 1, n = sp.nb[seg];
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -514,6 +637,7 @@ __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, Sor
       sc += red4[k][3];
     }
     counts[1] = (int)sc;
+    if (sorting) counts[5] += 1;
     scal[0] = sa;
     scal[1] = sb;
     scal[2] = sm;
@@ -531,7 +655,9 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_stage(const R *__restrict__
                                                            const int *__restrict__ key_c,
                                                            const int *__restrict__ hist,
                                                            const int *__restrict__ bbase, real4<R> *stg_t,
-                                                           int2 *ik_t, real4<R> *stg_c, int2 *ik_c) {
+                                                           int2 *ik_t, real4<R> *stg_c, int2 *ik_c,
+                                                           const int *need) {
+  if (need && *need == 0) return;
   constexpr int U = kSortChunkMax / kSortBlock;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int nbk = sp.nb[0] + sp.nb[1];
@@ -644,7 +770,9 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
                                                               const real4<R> *__restrict__ stg_c,
                                                               const int2 *__restrict__ ik_c, int *srank_c,
                                                               real4<R> *part_t, int *perm_t, int *off_t,
-                                                              real4<R> *part_c, int *perm_c, int *off_c) {
+                                                              real4<R> *part_c, int *perm_c, int *off_c,
+                                                              const int *need) {
+  if (need && *need == 0) return;
   constexpr int U = kSortFineRegs;
   extern __shared__ int lds_fine[];
   const bool tiles = (int)blockIdx.x < sp.nb[0];
@@ -2311,7 +2439,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
 
 // energy parts in FP64: (total, E_R, E_K, E_self, E_bg)
 __global__ __launch_bounds__(1024) void k_finalize(const double *kpart, int nk, const double *rpart, int nr,
-                                                  const double *scal, Geom g, double *E) {
+                                                  const double *scal, Geom g, double *E, int *counts) {
   // eight independent partial sums per thread keep eight loads in flight
   auto sum = [](const double *v, int n) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -2339,6 +2467,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *kpart, int nk, 
     E[2] = ek;
     E[3] = es;
     E[4] = eb;
+    counts[3] = 0;  // persistent binning: the next evaluation decides afresh
   }
 }
 
@@ -2567,7 +2696,9 @@ __global__ __launch_bounds__(256) void k_init_ws(Geom g, TabOff t, R *__restrict
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     build_runs(g, runs);
-    for (int j = 0; j < 4; ++j) counts[j] = 0;
+    for (int j = 0; j < 8; ++j) counts[j] = 0;
+    counts[3] = 1;   // the first evaluation on a workspace sorts
+    counts[4] = -1;  // no all-active flag seen yet
   }
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < 2 * kESlots; j += blockDim.x) eslot[j] = 0.0;
@@ -2622,9 +2753,13 @@ enum GatherKind { kGatherIk = 0, kGatherGrad4 = 1, kGatherGradScalar = 2 };
 template <typename R, int P, bool GRAD, typename FT>
 static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R ss, R *vo, R *so) {
   // a potential-only grid stages 2 x 2 spread tiles (y, z) per block (less
-  // halo per point, more particles per block); the interleaved fields one
+  // halo per point, more particles per block); the interleaved fields one.
+  // Under persistent binning particles may have left their tile (by less
+  // than the skin), so the direct form, which reads the grid per particle,
+  // is used.
+  const bool persist = g.skin > 0.0;
   const size_t lds2 = gather_tile_lds<FT, P>(g, 2, 2);
-  if (sizeof(FT) == sizeof(R) && lds2 <= 65536) {
+  if (!persist && sizeof(FT) == sizeof(R) && lds2 <= 65536) {
     const int nb = g.nt[0] * ((g.nt[1] + 1) / 2) * ((g.nt[2] + 1) / 2);
     hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2, kGatherLanesBig>), dim3(nb), dim3(kGatherTileBlock), lds2, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
@@ -2632,7 +2767,7 @@ static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pre
     return;
   }
   const size_t lds = gather_tile_lds<FT, P>(g, 1, 1);
-  if (lds <= 65536) {
+  if (!persist && lds <= 65536) {
     hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 1, 1, kGatherLanes>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
                        so);
@@ -2698,23 +2833,37 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   const int nbk = sp.nb[0] + sp.nb[1];
   const size_t lds_cnt = (size_t)nbk * sizeof(int);
   const size_t lds_fine = sort_fine_lds(sp);
+  // persistent binning: the check decides (on the device) whether this
+  // evaluation sorts; the sort passes and the refresh both launch and the
+  // ones not needed return at once
+  const bool persist = g.skin > 0.0;
+  const int *need = persist ? w.counts + 3 : nullptr;
+  if (persist)
+    hipLaunchKernelGGL((k_persist_check<R>), dim3(std::min(1024, (g.n + kSortBlock - 1) / kSortBlock)),
+                       dim3(kSortBlock), 0, st, x, q, g, (const R *)w.x_ref, (const R *)w.q_ref,
+                       all_active ? 1 : 0, w.counts);
   hipLaunchKernelGGL((k_sort_count<R>), dim3(sp.nblk), dim3(kSortBlock), lds_cnt, st, x, q, g, sp,
-                     all_active ? 1 : 0, w.key_t, w.key_c, w.hist, F, phi, w.qpart, w.counts);
+                     all_active ? 1 : 0, w.key_t, w.key_c, w.hist, F, phi, w.qpart, w.counts, persist ? 1 : 0,
+                     (R *)w.x_ref, (R *)w.q_ref, w.act);
+  if (persist)
+    hipLaunchKernelGGL((k_refresh<R>), dim3(sp.nblk), dim3(kSortBlock), 0, st, x, q, g, sp, (const R *)w.x_ref,
+                       (const int *)w.act, (const int *)w.perm_t, (const int *)w.perm_c, (real4<R> *)w.part_t,
+                       (real4<R> *)w.part_c, F, phi, w.qpart, (const int *)w.counts);
   ENUF_TRY(hipGetLastError());
   mark(1);
   // sort: slots, bucket staging, fine sort per bucket (the key arrays are
   // dead after staging and take the fine ranks)
   hipLaunchKernelGGL(k_sort_colscan, dim3((nbk + kColW - 1) / kColW), dim3(kColW * kColG), 0, st, w.hist, sp,
-                     w.bbase);
+                     w.bbase, need);
   hipLaunchKernelGGL(k_sort_base, dim3(1), dim3(1024), 0, st, w.bbase, sp, w.off_t, w.off_c,
-                     (const double *)w.qpart, w.scal, w.counts, w.eslot);
+                     (const double *)w.qpart, w.scal, w.counts, w.eslot, persist ? 1 : 0);
   hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
                      x, q, g, sp, (const int *)w.key_t, (const int *)w.key_c, (const int *)w.hist,
-                     (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c);
+                     (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c, need);
   hipLaunchKernelGGL((k_sort_fine<R>), dim3(nbk), dim3(kSortFineBlock), lds_fine, st, sp, (const int *)w.bbase,
                      (const real4<R> *)w.stg_t, (const int2 *)w.ik_t, w.key_t, (const real4<R> *)w.stg_c,
                      (const int2 *)w.ik_c, w.key_c, (real4<R> *)w.part_t, w.perm_t, w.off_t,
-                     (real4<R> *)w.part_c, w.perm_c, w.off_c);
+                     (real4<R> *)w.part_c, w.perm_c, w.off_c, need);
   ENUF_TRY(hipGetLastError());
   mark(2);
   // spread
@@ -2770,7 +2919,7 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   ENUF_TRY(hipGetLastError());
   mark(8);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, (const double *)w.eslot, kESlots,
-                     (const double *)(w.eslot + kESlots), kESlots, (const double *)w.scal, g, E);
+                     (const double *)(w.eslot + kESlots), kESlots, (const double *)w.scal, g, E, w.counts);
   ENUF_TRY(hipGetLastError());
   mark(9);
   return hipSuccess;

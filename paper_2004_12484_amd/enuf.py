@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libenuf.so")
 
 ENUF_OK, ENUF_EINVAL, ENUF_ENOMEM, ENUF_EDEVICE, ENUF_ENONFINITE, ENUF_ESTATE, ENUF_EUNSUPPORTED = range(7)
 ENUF_FP64, ENUF_FP32 = 0, 1
-OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE, OPT_SLATER, OPT_WINDOW, OPT_OVERSAMPLING = range(8)
+(OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE, OPT_SLATER, OPT_WINDOW, OPT_OVERSAMPLING,
+ OPT_SKIN) = range(9)
 WINDOWS = {"bspline": 0, "gaussian": 1}
 FORCE_MODES = {"ik": 0, "analytic": 1}
 STAGE_GRID, STAGE_SPECTRUM, STAGE_FIELDS, STAGE_SORTED, STAGE_COUNTS, STAGE_CELLS = range(6)
@@ -104,13 +105,15 @@ class Enuf:
     """
 
     def __init__(self, box, n, alpha, r_c, M, p, precision="f64", ke=1.0, device=None, check=False,
-                 force_mode="ik", slater=None, workspace=True, window="bspline", oversampling=1.0):
+                 force_mode="ik", slater=None, workspace=True, window="bspline", oversampling=1.0, skin=0.0):
         """slater: decay length lambda_e of ENUF-DPD Slater-type smeared
         charges (paper Sec. 2.4); None for point charges.  workspace: give
         the context a workspace held in a torch uint8 tensor (False: none).
         window ("bspline" or "gaussian", the paper's NFFT window of cutoff
         m = p/2 - 1) and oversampling (sigma >= 1: only the modes |n_d| <
-        K_d/2, K_d = 2 floor(M_d / 2 sigma), are kept)."""
+        K_d/2, K_d = 2 floor(M_d / 2 sigma), are kept).  skin > 0: persistent
+        binning for MD (the sort is kept while no particle has moved more
+        than skin/2)."""
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("ENUF needs a HIP GPU; torch.cuda.is_available() is False")
@@ -135,6 +138,8 @@ class Enuf:
                 msg = lib.enuf_last_error(None).decode(errors="replace")
                 raise EnufError(st, msg)
         self._ws = None
+        if skin:
+            self.set_option(OPT_SKIN, float(skin))
         if workspace:
             nb = ctypes.c_size_t()
             _check(lib.enuf_workspace_bytes(self._h, ctypes.byref(nb)), self._h)
