@@ -486,37 +486,67 @@ __global__ __launch_bounds__(kSortBlock) void k_refresh(const R *__restrict__ x,
       if (phi) phi[i] = R(0);
     }
   }
-  const int na = counts[0];
-  for (int k = (int)i0 + threadIdx.x; k < min(i1, na); k += blockDim.x) {
-    {
-      const int i = perm_t[k];
-      const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
-      R xw[3], sg[3];
-      particle_coords(p3, g, xw, sg);
-      real4<R> a;
-      a.x = sg[0];
-      a.y = sg[1];
-      a.z = sg[2];
-      a.w = q[i];
-      part_t[k] = a;
-    }
-    {
-      const int i = perm_c[k];
-      const R r3[3] = {x_ref[3 * i], x_ref[3 * i + 1], x_ref[3 * i + 2]};
-      R xw[3], sg[3];
-      particle_coords(r3, g, xw, sg);
-      real4<R> a;
-      R d[3];
+  // the kept orders gather from the caller's arrays at random: four slots
+  // per thread, their loads issued together
+  const int ke = min(i1, counts[0]);
+  constexpr int U = 4;
+  for (int kb = (int)i0 + threadIdx.x; kb < ke; kb += U * blockDim.x) {
+    int it[U], ic[U];
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        d[e] = x[3 * i + e] - r3[e];
-        d[e] -= R(g.L[e]) * rint(d[e] * R(g.iL[e]));
+    for (int u = 0; u < U; ++u) {
+      const int k = kb + u * blockDim.x;
+      it[u] = k < ke ? perm_t[k] : 0;
+      ic[u] = k < ke ? perm_c[k] : 0;
+    }
+    R pt[U][4], pc[U][4], pr[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      pt[u][0] = x[3 * it[u]];
+      pt[u][1] = x[3 * it[u] + 1];
+      pt[u][2] = x[3 * it[u] + 2];
+      pt[u][3] = q[it[u]];
+      pc[u][0] = x[3 * ic[u]];
+      pc[u][1] = x[3 * ic[u] + 1];
+      pc[u][2] = x[3 * ic[u] + 2];
+      pc[u][3] = q[ic[u]];
+      pr[u][0] = x_ref[3 * ic[u]];
+      pr[u][1] = x_ref[3 * ic[u] + 1];
+      pr[u][2] = x_ref[3 * ic[u] + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kb + u * blockDim.x;
+      if (k >= ke) break;
+      {
+        const R p3[3] = {pt[u][0], pt[u][1], pt[u][2]};
+        R xw[3], sg[3];
+        particle_coords(p3, g, xw, sg);
+        real4<R> a;
+        a.x = sg[0];
+        a.y = sg[1];
+        a.z = sg[2];
+        a.w = pt[u][3];
+        part_t[k] = a;
       }
-      a.x = xw[0] + d[0];
-      a.y = xw[1] + d[1];
-      a.z = xw[2] + d[2];
-      a.w = q[i];
-      part_c[k] = a;
+      {
+        // the position at the last sort, wrapped as the sort wrapped it, plus
+        // the minimum-image displacement since
+        const R r3[3] = {pr[u][0], pr[u][1], pr[u][2]};
+        R xw[3], sg[3];
+        particle_coords(r3, g, xw, sg);
+        R d[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          d[e] = pc[u][e] - r3[e];
+          d[e] -= R(g.L[e]) * rint(d[e] * R(g.iL[e]));
+        }
+        real4<R> a;
+        a.x = xw[0] + d[0];
+        a.y = xw[1] + d[1];
+        a.z = xw[2] + d[2];
+        a.w = pc[u][3];
+        part_c[k] = a;
+      }
     }
   }
   const double a = block_sum(qs);
@@ -1924,8 +1954,13 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
   const int tz0 = SZ * (t / nsy);
   const int nys = min(SY, g.nt[1] - ty0), nzs = min(SZ, g.nt[2] - tz0);
   const int t0[3] = {tx * g.T[0], ty0 * g.T[1], tz0 * g.T[2]};
-  const int E0 = g.T[0] + P - 1, E1 = nys * g.T[1] + P - 1, E2 = nzs * g.T[2] + P - 1;
-  const int e0x = t0[0] - P / 2 + 1, e0y = t0[1] - P / 2 + 1, e0z = t0[2] - P / 2 + 1;
+  // with persistent binning a particle may sit up to sdig points outside its
+  // tile: the region grows by that margin on each side
+  const int D0 = g.sdig[0], D1 = g.sdig[1], D2 = g.sdig[2];
+  const int E0 = g.T[0] + P - 1 + 2 * D0, E1 = nys * g.T[1] + P - 1 + 2 * D1, E2 = nzs * g.T[2] + P - 1 + 2 * D2;
+  const int e0x = t0[0] - P / 2 + 1 - D0, e0y = t0[1] - P / 2 + 1 - D1, e0z = t0[2] - P / 2 + 1 - D2;
+  const int span[3] = {g.T[0], nys * g.T[1], nzs * g.T[2]};
+  const int marg[3] = {D0, D1, D2};
   {
     // the block's region plus halo, as one flat index over (z, y, x): eight
     // loads in flight per lane before any is written to LDS; no wrapping
@@ -2008,6 +2043,15 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       fl = floor(v.z);
       l[2] = (int)fl - t0[2];
       if (GRAD) window_wd<R, P>(v.z - fl, wz, dz, g); else window_w<R, P>(v.z - fl, wz, g);
+      // a particle that moved across the periodic boundary (persistent
+      // binning) comes back within the margin of its tile; offset into the
+      // region past the margin
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (l[d] >= span[d] + marg[d]) l[d] -= g.M[d];
+        else if (l[d] < -marg[d]) l[d] += g.M[d];
+        l[d] += marg[d];
+      }
     }
     R a0s = 0, a1s = 0, a2s = 0, a3s = 0;
     // this lane's (z, y) rows: with four lanes z = za + 2m, y = yb + 2n (za,
@@ -2743,7 +2787,8 @@ static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
 }
 template <typename FT, int P>
 static size_t gather_tile_lds(const Geom &g, int sy, int sz) {
-  return (size_t)(g.T[0] + P - 1) * (sy * g.T[1] + P - 1) * (sz * g.T[2] + P - 1) * sizeof(FT);
+  return (size_t)(g.T[0] + P - 1 + 2 * g.sdig[0]) * (sy * g.T[1] + P - 1 + 2 * g.sdig[1]) *
+         (sz * g.T[2] + P - 1 + 2 * g.sdig[2]) * sizeof(FT);
 }
 // Gather kinds: ik forces and potentials from the interleaved (E, psi) grid;
 // gradient form (forces -dE/dr or the adjoint dE/dr, scaled by gs, and the
@@ -2754,12 +2799,11 @@ template <typename R, int P, bool GRAD, typename FT>
 static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pref, R gs, R ss, R *vo, R *so) {
   // a potential-only grid stages 2 x 2 spread tiles (y, z) per block (less
   // halo per point, more particles per block); the interleaved fields one.
-  // Under persistent binning particles may have left their tile (by less
-  // than the skin), so the direct form, which reads the grid per particle,
-  // is used.
-  const bool persist = g.skin > 0.0;
+  // Under persistent binning particles may have left their tile by up to
+  // sdig points: the staged region carries that margin, and the direct form
+  // (grid read per particle) takes over when it no longer fits.
   const size_t lds2 = gather_tile_lds<FT, P>(g, 2, 2);
-  if (!persist && sizeof(FT) == sizeof(R) && lds2 <= 65536) {
+  if (sizeof(FT) == sizeof(R) && lds2 <= 65536) {
     const int nb = g.nt[0] * ((g.nt[1] + 1) / 2) * ((g.nt[2] + 1) / 2);
     hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2, kGatherLanesBig>), dim3(nb), dim3(kGatherTileBlock), lds2, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
@@ -2767,7 +2811,7 @@ static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pre
     return;
   }
   const size_t lds = gather_tile_lds<FT, P>(g, 1, 1);
-  if (!persist && lds <= 65536) {
+  if (lds <= 65536) {
     hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 1, 1, kGatherLanes>), dim3(g.ntiles), dim3(kGatherTileBlock), lds, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
                        so);
