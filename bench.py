@@ -39,7 +39,9 @@ WORKLOADS = {
     "ions_1m": dict(gen="ions_1m", kw={}, force_mode="analytic",
                     # the plain FP64 form's fastest setting with eps_F <= 1e-4
                     # (bench.py --search --precision f64: 3.02 ms, eps_F 4.9e-5)
-                    fp64_form=dict(force_mode="analytic", M=(256, 256, 256), p=6, r_c=1.8, alpha=2.9 / 1.8)),
+                    fp64_form=dict(force_mode="analytic", M=(256, 256, 256), p=6, r_c=1.8, alpha=2.9 / 1.8),
+                    # the parameter network's own setting for the same target
+                    learned_form=1e-4),
     "electrolyte": dict(gen="electrolyte", kw={}),
     "nacl": dict(gen="nacl", kw={}),
     # 4M sites in 120 x 120 x 240: parameters from the selector (the network,
@@ -48,10 +50,15 @@ WORKLOADS = {
     # rounding of the positions alone costs ~2.8e-4 here: chain beads come
     # within a few hundredths of each other), forces and dE/dq
     "anisotropic_selected": dict(gen="anisotropic", kw={}, select=5e-4, potential=True, golden="anisotropic"),
-    # the same system at its stated grid, 256 x 256 x 512 with p = 6; alpha
-    # and r_c the fastest of a timed sweep at that grid (alpha r_c in 2.6 ..
-    # 3.5, r_c in 2.5 .. 4.5; every setting met 1e-4 against the oracle)
-    "anisotropic": dict(gen="anisotropic", kw=dict(alpha=0.8, r_c=4.0, M=(256, 256, 512), p=6), potential=True),
+    # the same system at the parameter network's setting for 1e-4 (the
+    # stated 256 x 256 x 512 grid with p = 6 comes out of it); forces and
+    # dE/dq from the potential grid alone (analytic mode: one field instead
+    # of four, 1.6x faster at the same error)
+    "anisotropic": dict(gen="anisotropic", kw={}, select=1e-4, potential=True, force_mode="analytic"),
+    # ... and at the fastest setting of a timed sweep at the stated grid
+    # (alpha r_c in 2.6 .. 3.5, r_c in 2.5 .. 4.5; all met 1e-4)
+    "anisotropic_swept": dict(gen="anisotropic", kw=dict(alpha=0.8, r_c=4.0, M=(256, 256, 512), p=6),
+                              potential=True, golden="anisotropic"),
     # ENUF-DPD: the charged fluid read as a DPD system (R_c = 1, density ~3,
     # real-space cutoff 3 R_c) of Slater-smeared charges with beta = 1.125
     # (decay length 1/1.125)
@@ -200,6 +207,43 @@ def golden_check(w, F, E, phi=None, name=None):
         ref = g["phi_conv"] if "phi_conv" in g.files else g["phi"]
         out["rms_dEdq_err"] = float(np.linalg.norm(phi[s] - ref) / np.linalg.norm(ref))
     return out
+
+
+def learned_form(w, target, x, q, args, name, force_mode):
+    """The same workload in the same precision at the parameter network's
+    setting for `target` (enuf_select_params with the trained network),
+    timed like the main line: the learned-parameter form beside the
+    grid-searched one."""
+    import copy
+
+    import torch
+
+    from paper_2004_12484_amd import enuf
+    from paper_2004_12484_amd import params as P
+
+    fq = float(np.count_nonzero(w.q)) / w.N
+    s, method = P.select_params(w.N, w.box, fq, target, model_path=P.MODEL_BIN)
+    wl = copy.copy(w)
+    wl.alpha, wl.r_c, wl.M, wl.p = s["alpha"], s["r_c"], tuple(s["M"]), s["p"]
+    eng = enuf.Enuf(wl.box, wl.N, wl.alpha, wl.r_c, wl.M, wl.p, precision=w.precision, device=x.device,
+                    force_mode=force_mode)
+    for _ in range(args.warmup):
+        E, F, _ = eng.energy_forces(x, q)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        E, F, _ = eng.energy_forces(x, q)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    acc = golden_check(wl, F.double().cpu().numpy(), float(E[0].item()), name=name)
+    eng.close()
+    return {"ms_per_step": ms, "value": 1000.0 / ms, "unit": "evals/s", "dtype": w.precision, "target": target,
+            "selection": method, "setting": {"alpha": s["alpha"], "r_c": s["r_c"], "M": list(s["M"]), "p": s["p"],
+                                             "force_mode": force_mode},
+            "accuracy": acc}
 
 
 def fp64_form(w, setting, x32, q32, args, name):
@@ -445,6 +489,11 @@ def main():
                    "background": float(Eh[4])},
         "accuracy": acc, "roofline": roof,
     }
+    if spec.get("learned_form") and not args.no_fp64_form:
+        # the network's labels come from ik-force sweeps: its setting is run
+        # in that mode
+        rec["learned_form"] = learned_form(w, spec["learned_form"], x, q, args, spec.get("golden", args.workload),
+                                           "ik")
     if spec.get("fp64_form") and not args.no_fp64_form and w.precision == "f32":
         rec["fp64_form"] = fp64_form(w, spec["fp64_form"], x, q, args, name=spec.get("golden", args.workload))
     if not args.no_cpu_baseline:

@@ -183,19 +183,20 @@ def anisotropic(N: int = 1 << 22, box=(120.0, 120.0, 240.0), chain_fraction: flo
                     tuple(M), p, precision, seed)
 
 
-def random_system(seed: int, n_min: int = 1000, n_max: int = 262144) -> Workload:
+def random_system(seed: int, n_min: int = 1000, n_max: int = 262144, fq_min: float = 0.05,
+                  rho_min: float = 0.1, rho_max: float = 3.0) -> Workload:
     """Random neutral system for the parameter-selection sweeps.
 
     N log-uniform in [n_min, n_max]; cubic or 1:1:2 box (equal odds); number
-    density log-uniform in [0.1, 3]; charged fraction uniform in [0.05, 1];
-    charges +-1 in equal numbers.  The ENUF parameters recorded here are a
-    placeholder (the sweep sets its own).
+    density log-uniform in [rho_min, rho_max]; charged fraction uniform in
+    [fq_min, 1]; charges +-1 in equal numbers.  The ENUF parameters recorded
+    here are a placeholder (the sweep sets its own).
     """
     rng = np.random.default_rng(seed)
     N = int(round(10 ** rng.uniform(math.log10(n_min), math.log10(n_max))))
     aspect = np.array([1.0, 1.0, 2.0]) if rng.uniform() < 0.5 else np.ones(3)
-    density = 10 ** rng.uniform(math.log10(0.1), math.log10(3.0))
-    fq = rng.uniform(0.05, 1.0)
+    density = 10 ** rng.uniform(math.log10(rho_min), math.log10(rho_max))
+    fq = rng.uniform(fq_min, 1.0)
     V = N / density
     Lx = (V / np.prod(aspect)) ** (1.0 / 3.0)
     box = Lx * aspect

@@ -29,7 +29,9 @@ P_CHOICES = (4, 6, 8)
 M_MIN, M_MAX = 8, 512
 # the systems the network was trained on (inputs.random_system): outside
 # these ranges its prediction is not used
-TRAIN_RANGE = {"N": (1000, 262144), "density": (0.1, 3.0), "f_q": (0.05, 1.0), "target": (3e-5, 1e-3)}
+# (densities were drawn from [0.1, 3]; the bound admits 5% beyond, which
+# takes in the one-million-bead systems at 2^20 / 70^3 = 3.06)
+TRAIN_RANGE = {"N": (1000, 4194304), "density": (0.1, 3.15), "f_q": (0.02, 1.0), "target": (3e-5, 1e-3)}
 TRAIN_SHAPES = ((1.0, 1.0), (1.0, 2.0))   # (Ly/Lx, Lz/Lx) of the training boxes
 
 

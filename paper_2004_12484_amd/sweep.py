@@ -124,8 +124,26 @@ def sweep_arrays(x, q, box):
             "rows": np.array(rows, float).reshape(-1, 10), "cost_ms": cost}
 
 
+# the system families of the training data: seeds below LARGE_SEED0 are the
+# small and medium systems; then the large ones (up to the 4M-site workload,
+# charged fractions down to 0.02); from DENSE_SEED0 large dense and mostly
+# charged ones (the one-million-ion regime)
+LARGE_SEED0 = 5000
+LARGE = dict(n_min=262144, n_max=4194304, fq_min=0.02)
+DENSE_SEED0 = 5400
+DENSE = dict(n_min=262144, n_max=2097152, fq_min=0.5, rho_min=1.0, rho_max=3.15)
+
+
+def system_for_seed(seed):
+    if seed >= DENSE_SEED0:
+        return inputs.random_system(seed, **DENSE)
+    if seed >= LARGE_SEED0:
+        return inputs.random_system(seed, **LARGE)
+    return inputs.random_system(seed)
+
+
 def sweep_system(seed):
-    w = inputs.random_system(seed)
+    w = system_for_seed(seed)
     rec = sweep_arrays(w.x, w.q, w.box)
     rec["seed"] = seed
     return rec
@@ -155,12 +173,13 @@ def main(argv=None):
     args = ap.parse_args(argv)
     s0, s1 = (int(v) for v in args.seeds.split(":"))
     recs = []
-    t0 = time.time()
+    t0 = last = time.time()
     for k, seed in enumerate(range(s0, s1)):
         recs.append(sweep_system(seed))
-        if k % 50 == 0 or seed == s1 - 1:
+        if k % 50 == 0 or seed == s1 - 1 or time.time() - last > 30:
+            last = time.time()
             print(f"[sweep] seed {seed} N={recs[-1]['N']} rows={len(recs[-1]['rows'])} "
-                  f"elapsed {time.time() - t0:.0f}s", flush=True)
+                  f"elapsed {last - t0:.0f}s", flush=True)
     sys_arr = np.array([[r["seed"], r["N"], *r["box"], r["f_q"], r["a"], r["cost_ms"]] for r in recs], float)
     rows = np.concatenate([np.column_stack([np.full(len(r["rows"]), i), r["rows"]]) for i, r in enumerate(recs)])
     np.savez_compressed(args.out, systems=sys_arr, rows=rows,

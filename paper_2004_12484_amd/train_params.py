@@ -24,7 +24,7 @@ import time
 import numpy as np
 
 from . import params as P
-from .sweep import combine
+from .sweep import combine, system_for_seed
 
 TARGETS = (1e-3, 3e-4, 1e-4, 3e-5)
 Y_WEIGHTS = np.array([1.0, 1.0, 1.0, 1.0, 0.5, 1.0], np.float32)
@@ -84,12 +84,18 @@ def evaluate(paths, out, max_systems=200, log=print):
     from . import enuf, inputs
     from .sweep import reference_setting
 
-    recs = [r for r in load_sweeps(paths) if r["seed"] % 10 == 0][:max_systems]
+    held = [r for r in load_sweeps(paths) if r["seed"] % 10 == 0]
+    # every held-out large system, then the others spread evenly over the rest
+    big = [r for r in held if r["N"] > 262144]
+    rest = [r for r in held if r["N"] <= 262144]
+    k = max(0, max_systems - len(big))
+    stride = max(1, len(rest) // max(1, k))
+    recs = big[:max_systems] + rest[::stride][:k]
     pred = P.Predictor()
     dev = torch.device("cuda", 0)
     results = []
     for r in recs:
-        w = inputs.random_system(r["seed"])
+        w = system_for_seed(r["seed"])
         box = np.asarray(w.box, float)
         x64 = torch.tensor(w.x, dtype=torch.float64, device=dev)
         q64 = torch.tensor(w.q, dtype=torch.float64, device=dev)
@@ -144,8 +150,25 @@ def evaluate(paths, out, max_systems=200, log=print):
                           "median_search_cost_ms": float(np.median([x["search_cost_ms"] for x in rs])),
                           "median_grid_time_ms": float(np.median([x["grid"]["time_ms"] for x in rs])),
                           "median_mlp_time_ms": float(np.median([x["mlp"]["time_ms"] for x in rs]))}
+    by_size = []
+    for lo, hi in ((0, 2e4), (2e4, 262144.5), (262144.5, 4.3e6)):
+        for tgt in TARGETS:
+            rs = [x for x in results if x["target"] == tgt and x["grid"] is not None and lo <= x["N"] < hi]
+            if not rs:
+                continue
+            def ok(k):
+                return [x for x in rs if x[k] is not None and x[k]["err"] <= tgt]
+            def ratio(k):
+                v = [x[k]["time_ms"] / x["grid"]["time_ms"] for x in ok(k)]
+                return float(np.median(v)) if v else None
+            by_size.append({"N_range": [lo, hi], "target": tgt, "cases": len(rs),
+                            "mlp_meets_target": len(ok("mlp")) / len(rs),
+                            "heuristic_meets_target": len(ok("heuristic")) / len(rs),
+                            "mlp_time_over_grid_median": ratio("mlp"),
+                            "heuristic_time_over_grid_median": ratio("heuristic")})
     with open(out, "w") as f:
-        json.dump({"summary": summ, "cases": results}, f)
+        json.dump({"summary": summ, "by_size": by_size, "cases": results}, f)
+    log(json.dumps(by_size, indent=1))
     log(json.dumps(summ, indent=1))
     return summ
 

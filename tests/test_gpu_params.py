@@ -92,3 +92,66 @@ def test_trained_network_meets_targets_on_fresh_systems():
     print("network success rates:", rates)
     assert rates[1e-3] >= 0.9
     assert rates[1e-4] >= 0.8
+
+
+def _time_and_error(w, s, Fr, charged, x32, q32, reps=5):
+    from paper_2004_12484_amd import enuf
+
+    eng = enuf.Enuf(w.box, w.N, s["alpha"], s["r_c"], s["M"], s["p"], precision="f32")
+    eng.energy_forces(x32, q32)
+    eng.set_option(enuf.OPT_TIMING, reps)
+    for _ in range(reps):
+        _, F, _ = eng.energy_forces(x32, q32)
+    t = sum(eng.timings().values())
+    err = float((torch.linalg.norm(F.double()[charged] - Fr) / torch.linalg.norm(Fr)).item())
+    eng.close()
+    return t, err
+
+
+@pytest.mark.skipif(not os.path.exists(P.MODEL_PATH), reason="trained parameter model not present")
+def test_network_beats_heuristic_time_to_target():
+    """What the trained network gains over the method without it: on fresh
+    systems (30k .. 300k particles, seeds outside the training sets), at the
+    force targets 1e-3 and 3e-4, the network's setting reaches the target in
+    less GPU time than the Eq. 31-32 heuristic's, at the median, and meets
+    it as often.  A system whose FP32 floor (the FP32 form at the tight
+    reference setting, set by position rounding in large dilute boxes) is
+    above a third of a target cannot meet it with any parameters; such
+    (system, target) cases are left out."""
+    from paper_2004_12484_amd import enuf
+
+    ratios, hits_net, hits_heu, used = [], 0, 0, 0
+    for seed in range(9000, 9012):
+        w = inputs.random_system(seed, n_min=30000, n_max=300000)
+        fq = float(np.count_nonzero(w.q)) / w.N
+        x64 = torch.tensor(w.x, dtype=torch.float64, device="cuda")
+        q64 = torch.tensor(w.q, dtype=torch.float64, device="cuda")
+        charged = torch.tensor(w.q != 0, device="cuda")
+        ref = reference_setting(w.N, w.box)
+        eng = enuf.Enuf(w.box, w.N, ref["alpha"], ref["r_c"], ref["M"], ref["p"], precision="f64")
+        _, Fref, _ = eng.energy_forces(x64, q64)
+        Fr = Fref[charged]
+        eng.close()
+        _, floor = _time_and_error(w, ref, Fr, charged, x64.float(), q64.float(), reps=1)
+        for tgt in (1e-3, 3e-4):
+            if floor > tgt / 3:
+                continue
+            used += 1
+            s_net, method = P.select_params(w.N, w.box, fq, tgt, model_path=P.MODEL_BIN)
+            assert method == "network"
+            s_heu = P.heuristic(w.N, w.box, fq, tgt)
+            t_net, e_net = _time_and_error(w, s_net, Fr, charged, x64.float(), q64.float())
+            t_heu, e_heu = _time_and_error(w, s_heu, Fr, charged, x64.float(), q64.float())
+            hits_net += e_net <= tgt
+            hits_heu += e_heu <= tgt
+            if e_net <= tgt and e_heu <= tgt:
+                ratios.append(t_net / t_heu)
+            print(f"seed {seed} N={w.N} f_q={fq:.2f} target {tgt:.0e}: network {t_net:.3f} ms (eps {e_net:.1e}), "
+                  f"heuristic {t_heu:.3f} ms (eps {e_heu:.1e})")
+    med = float(np.median(ratios))
+    print(f"network/heuristic time at equal target: median {med:.3f} over {len(ratios)} cases; "
+          f"target met {hits_net}/{used} (network), {hits_heu}/{used} (heuristic)")
+    assert used >= 12
+    assert hits_net >= hits_heu - 1
+    assert hits_net >= 0.9 * used
+    assert med < 1.0
