@@ -127,7 +127,7 @@ typedef enum {
                                  on the stream and forgets the last
                                  evaluation (a following enuf_energy_grad
                                  reports ENUF_ESTATE). */
-    ENUF_OPT_SKIN = 8         /* persistent binning for MD (skin length
+    ENUF_OPT_SKIN = 8,        /* persistent binning for MD (skin length
                                  >= 0; default 0: every evaluation sorts).
                                  With skin s > 0 the particle orders of the
                                  last sort are kept while no particle has
@@ -148,6 +148,15 @@ typedef enum {
                                  workspace lays it out again (ENUF_ESTATE if
                                  it is too small) and forgets the last
                                  evaluation. */
+    ENUF_OPT_SPREAD_F16 = 9   /* FP32 contexts: products of the spread's
+                                 tile contraction.  0 (default): FP32 matrix
+                                 products with FP32 accumulation.  1: each
+                                 operand split into two half-precision parts
+                                 and the product taken as three
+                                 half-precision matrix products (hi*hi +
+                                 hi*lo + lo*hi, ~21 significant bits per
+                                 product, FP32 accumulation): faster, not
+                                 FP32 arithmetic.  No effect in FP64. */
 } enuf_option;
 
 /* Internal buffers enuf_stage_copy() can read (for tests of single steps). */

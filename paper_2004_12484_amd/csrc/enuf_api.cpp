@@ -42,6 +42,7 @@ struct GraphCache {
   double ke = 0.0, slater = 0.0;
   int win = 0;
   double sigma = 1.0;
+  int spread16 = 0;
 };
 
 constexpr size_t kScratchBytes = ENUF_NOALLOC_SCRATCH_BYTES;
@@ -241,7 +242,7 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
   GraphCache &gc = c->gc;
   const bool hit = gc.exec && gc.x == x && gc.q == q && gc.E == E && gc.F == F && gc.phi == phi &&
                    gc.ws == c->w.grid && gc.analytic == an && gc.ke == c->g.ke && gc.slater == c->g.slater &&
-                   gc.win == c->g.win && gc.sigma == c->g.sigma;
+                   gc.win == c->g.win && gc.sigma == c->g.sigma && gc.spread16 == c->g.spread16;
   if (!hit) {
     drop_graph(c);
     hipGraph_t graph = nullptr;
@@ -270,6 +271,7 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
     gc.slater = c->g.slater;
     gc.win = c->g.win;
     gc.sigma = c->g.sigma;
+    gc.spread16 = c->g.spread16;
   }
   hipError_t e = hipEventRecord(c->gev[0], c->st);
   if (e == hipSuccess) e = hipStreamWaitEvent(c->gst, c->gev[0], 0);
@@ -344,6 +346,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   g.gb = g.gib = 0.0;
   g.sigma = 1.0;
   for (int d = 0; d < 3; ++d) g.kept[d] = g.M[d];
+  g.spread16 = 0;
 
   const size_t rs = precision == ENUF_FP64 ? 8 : 4;
   if (!enuf::fft_plans_fit(g, precision == ENUF_FP64))
@@ -506,6 +509,11 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       }
       return ENUF_OK;
     }
+    case ENUF_OPT_SPREAD_F16:
+      if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "spread product mode is 0 or 1");
+      ctx->g.spread16 = (int)value;
+      drop_graph(ctx);
+      return ENUF_OK;
     case ENUF_OPT_WINDOW:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "window is 0 (B-spline) or 1 (Gaussian)");
       if (value == 1.0 && ctx->g.p < 4) return fail(ctx, ENUF_EINVAL, "the Gaussian window needs p >= 4 (cutoff m = p/2 - 1 >= 1)");

@@ -59,6 +59,9 @@ struct Geom {
   // tile spill classes a margin of sdig[d] grid points
   double skin;
   int sdig[3];
+  // FP32 spread products: 0 FP32 matrix products; 1 split half-precision
+  // products (three f16 products per pair of operands, ~21 bits)
+  int spread16;
 };
 
 // Two-level counting sort layout: particles are counted in `nblk` blocks of

@@ -1154,7 +1154,7 @@ __device__ void tile_runs(const int *__restrict__ off_t, const int *__restrict__
   __syncthreads();
 }
 
-template <int P>
+template <int P, bool F32MAC>
 __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ part, const int *__restrict__ off_t,
                                                      const int *__restrict__ runs, int nruns, Geom g,
                                                      const double *__restrict__ scal, float *__restrict__ grid) {
@@ -1241,16 +1241,29 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
       for (int r = 0; r < 4; ++r)
         if (k0 + r >= ns) a[r] = 0.0f;
       const float4_t by = *reinterpret_cast<const float4_t *>(&E[16 + (lane & 7)][k0]);
-      half4_t ah, al;
-      split_f16(a, ah, al);
+      if constexpr (F32MAC) {
+        // FP32 products: four 16x16x4 FP32 MFMAs per column block, the j-th
+        // taking element j of every lane's four staged particles (so the
+        // four cover the step's 16 particles; A and B use the same order)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const float4_t bz = *reinterpret_cast<const float4_t *>(&E[24 + 2 * nb + ((lane >> 3) & 1)][k0]);
-        half4_t bh, bl;
-        split_f16(by * bz, bh, bl);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, acc[nb], 0, 0, 0);
+        for (int nb = 0; nb < 4; ++nb) {
+          const float4_t bz = *reinterpret_cast<const float4_t *>(&E[24 + 2 * nb + ((lane >> 3) & 1)][k0]);
+          const float4_t b = by * bz;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[nb], 0, 0, 0);
+        }
+      } else {
+        half4_t ah, al;
+        split_f16(a, ah, al);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const float4_t bz = *reinterpret_cast<const float4_t *>(&E[24 + 2 * nb + ((lane >> 3) & 1)][k0]);
+          half4_t bh, bl;
+          split_f16(by * bz, bh, bl);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, acc[nb], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -2778,10 +2791,14 @@ __global__ void k_scale_dev(R *__restrict__ a, long long n, const double *__rest
 
 template <typename R, int P>
 static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
-  if constexpr (sizeof(R) == 4)
-    hipLaunchKernelGGL((k_spread_mfma<P>), dim3(g.ntiles), dim3(256), 0, st, (const float4 *)w.part_t, w.off_t,
-                       (const int *)w.runs, w.nruns, g, (const double *)w.scal, (float *)w.grid);
-  else
+  if constexpr (sizeof(R) == 4) {
+    if (g.spread16)
+      hipLaunchKernelGGL((k_spread_mfma<P, false>), dim3(g.ntiles), dim3(256), 0, st, (const float4 *)w.part_t,
+                         w.off_t, (const int *)w.runs, w.nruns, g, (const double *)w.scal, (float *)w.grid);
+    else
+      hipLaunchKernelGGL((k_spread_mfma<P, true>), dim3(g.ntiles), dim3(256), 0, st, (const float4 *)w.part_t,
+                         w.off_t, (const int *)w.runs, w.nruns, g, (const double *)w.scal, (float *)w.grid);
+  } else
     hipLaunchKernelGGL((k_spread<R, P>), dim3(g.ntiles), dim3(spread_block<R>()), 0, st,
                        (const real4<R> *)w.part_t, w.off_t, (const int *)w.runs, w.nruns, g, (R *)w.grid);
 }

@@ -291,3 +291,29 @@ def test_nonfinite_input_is_flagged_and_excluded():
     assert abs(out["E"][0] - m["E"]) <= TOL64_E * _enorm(m)
     assert rms_rel(out["F"][keep], m["F"]) <= TOL64_F
     assert np.all(out["F"][~keep] == 0.0)
+
+
+@pytest.mark.parametrize("spread_f16", [0, 1])
+def test_fp32_wide_charge_range_vs_mirror(spread_f16):
+    """Charges spanning four decades (|q| log-uniform in [1e-3, 10]): the
+    FP32 form against the mirror at the FP32 tolerance, with FP32 products in
+    the spread (default) and with split half-precision products, where the
+    small charges' operands fall into the half-precision subnormal range."""
+    from paper_2004_12484_amd import enuf
+
+    rng = np.random.default_rng(77)
+    n, box = 2000, np.array([11.0, 12.0, 13.0])
+    x = rng.uniform(0, 1, (n, 3)) * box
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * 10 ** rng.uniform(-3, 1, n)
+    q -= q.mean()
+    x, q = _as_precision(x, q, "f32")
+    M, p, alpha, rc = (32, 32, 64), 6, 1.1, 4.0
+    eng = enuf.Enuf(box, n, alpha, rc, M, p, precision="f32")
+    eng.set_option(enuf.OPT_SPREAD_F16, spread_f16)
+    _, out = run(x, q, box, alpha, rc, M, p, precision="f32", eng=eng)
+    m = em.enuf(x, q, box, alpha, rc, M, p, want_grad=False)
+    _compare(out, m, "f32")
+    # the small charges' forces and potentials, relative to their own size
+    small = np.abs(q) < 1e-2
+    assert rms_rel(out["F"][small], m["F"][small]) <= TOL32_F
+    assert rms_rel(out["phi"][small], m["phi"][small]) <= TOL32_F
