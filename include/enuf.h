@@ -148,7 +148,7 @@ typedef enum {
                                  workspace lays it out again (ENUF_ESTATE if
                                  it is too small) and forgets the last
                                  evaluation. */
-    ENUF_OPT_SPREAD_F16 = 9   /* FP32 contexts: products of the spread's
+    ENUF_OPT_SPREAD_F16 = 9,  /* FP32 contexts: products of the spread's
                                  tile contraction.  0 (default): FP32 matrix
                                  products with FP32 accumulation.  1: each
                                  operand split into two half-precision parts
@@ -157,6 +157,16 @@ typedef enum {
                                  hi*lo + lo*hi, ~21 significant bits per
                                  product, FP32 accumulation): faster, not
                                  FP32 arithmetic.  No effect in FP64. */
+    ENUF_OPT_DETERMINISTIC = 10 /* 1: run-to-run bitwise reproducible
+                                 results for the same inputs and options on
+                                 the same device: after each sort the
+                                 particles of every bin are put in caller-index
+                                 order (so spread, pair and energy sums run in
+                                 one order).  A bin of more than 4096
+                                 particles cannot be ordered: flag bit 1
+                                 (enuf_get_flags) is set.  Default 0.  The
+                                 energy partials are summed in a fixed order
+                                 in either mode. */
 } enuf_option;
 
 /* Internal buffers enuf_stage_copy() can read (for tests of single steps). */
@@ -313,7 +323,8 @@ enuf_status enuf_energy_forces_noalloc(enuf_ctx ctx, const void *x, const void *
                                        void *F, void *phi);
 
 /* enuf_get_flags -- synchronise the stream and return the sticky device
- * flags (bit 0: non-finite input seen); clears them. */
+ * flags (bit 0: non-finite input seen; bit 1: a bin too large for the
+ * deterministic order); clears them. */
 enuf_status enuf_get_flags(enuf_ctx ctx, int32_t *flags);
 
 /* enuf_stage_copy -- synchronously copy an internal buffer (enuf_stage) of

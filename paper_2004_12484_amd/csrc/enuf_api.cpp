@@ -43,6 +43,7 @@ struct GraphCache {
   int win = 0;
   double sigma = 1.0;
   int spread16 = 0;
+  int det = 0;
 };
 
 constexpr size_t kScratchBytes = ENUF_NOALLOC_SCRATCH_BYTES;
@@ -172,7 +173,7 @@ static size_t layout(const Geom &g, size_t rs, char *base, Work *w) {
   t.act = (int *)take(n * 4);
   t.scal = (double *)take(4 * 8);
   t.qpart = (double *)take((size_t)4 * sp.nblk * 8);
-  t.eslot = (double *)take((size_t)2 * enuf::kESlots * 8);
+  t.eslot = (double *)take(enuf::eslot_len(g) * 8);
   t.grid = take(G * rs);
   t.spec = take(G / 2 * 2 * rs);
   t.fspec = take(4 * (G / 2) * 2 * rs);
@@ -242,7 +243,8 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
   GraphCache &gc = c->gc;
   const bool hit = gc.exec && gc.x == x && gc.q == q && gc.E == E && gc.F == F && gc.phi == phi &&
                    gc.ws == c->w.grid && gc.analytic == an && gc.ke == c->g.ke && gc.slater == c->g.slater &&
-                   gc.win == c->g.win && gc.sigma == c->g.sigma && gc.spread16 == c->g.spread16;
+                   gc.win == c->g.win && gc.sigma == c->g.sigma && gc.spread16 == c->g.spread16 &&
+                   gc.det == c->g.det;
   if (!hit) {
     drop_graph(c);
     hipGraph_t graph = nullptr;
@@ -272,6 +274,7 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
     gc.win = c->g.win;
     gc.sigma = c->g.sigma;
     gc.spread16 = c->g.spread16;
+    gc.det = c->g.det;
   }
   hipError_t e = hipEventRecord(c->gev[0], c->st);
   if (e == hipSuccess) e = hipStreamWaitEvent(c->gst, c->gev[0], 0);
@@ -347,6 +350,7 @@ enuf_status enuf_create(enuf_ctx *out, const double box[3], int64_t n, double al
   g.sigma = 1.0;
   for (int d = 0; d < 3; ++d) g.kept[d] = g.M[d];
   g.spread16 = 0;
+  g.det = 0;
 
   const size_t rs = precision == ENUF_FP64 ? 8 : 4;
   if (!enuf::fft_plans_fit(g, precision == ENUF_FP64))
@@ -509,6 +513,11 @@ enuf_status enuf_set_option(enuf_ctx ctx, int32_t option, double value) {
       }
       return ENUF_OK;
     }
+    case ENUF_OPT_DETERMINISTIC:
+      if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "deterministic is 0 or 1");
+      ctx->g.det = (int)value;
+      drop_graph(ctx);
+      return ENUF_OK;
     case ENUF_OPT_SPREAD_F16:
       if (value != 0.0 && value != 1.0) return fail(ctx, ENUF_EINVAL, "spread product mode is 0 or 1");
       ctx->g.spread16 = (int)value;

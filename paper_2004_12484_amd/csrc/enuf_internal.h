@@ -30,7 +30,9 @@ constexpr int kSortChunkMax = 2048;  // particles grouped in LDS at a time by th
 constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass
 constexpr int kSortFineRegs = 8;     // particles per thread held in registers by the fine pass
 constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)
-constexpr int kESlots = 64;    // energy partial sums per part (blocks add into slot = block mod 64)
+constexpr int kESlots = 64;    // energy partials per part outside the deterministic mode (block mod 64)
+constexpr int kDetSmall = 32;  // deterministic bin order: bins up to this size sorted by one thread
+constexpr int kDetBig = 4096;  // ... and up to this size by one workgroup in LDS
 
 // Geometry and parameters, passed by value to kernels.
 struct Geom {
@@ -62,7 +64,18 @@ struct Geom {
   // FP32 spread products: 0 FP32 matrix products; 1 split half-precision
   // products (three f16 products per pair of operands, ~21 bits)
   int spread16;
+  int det;         // deterministic mode: particles within every bin in caller-index order
 };
+// Work::eslot: the reciprocal partials (one per z-pass block, at most
+// (Mx/2) My, and at least the kESlots atomic slots), then the real-space ones
+// (one per cell, at least kESlots)
+inline size_t eslot_real_off(const Geom &g) {
+  const size_t n = (size_t)(g.M[0] / 2) * g.M[1];
+  return n > (size_t)kESlots ? n : (size_t)kESlots;
+}
+inline size_t eslot_len(const Geom &g) {
+  return eslot_real_off(g) + ((size_t)g.ncells > (size_t)kESlots ? (size_t)g.ncells : (size_t)kESlots);
+}
 
 // Two-level counting sort layout: particles are counted in `nblk` blocks of
 // `per`; the keys of order o (0 tile, 1 cell) are cut into nb[o] buckets of
@@ -105,7 +118,9 @@ struct Work {
   int *act = nullptr;       // [n] 1 for particles active at the last sort
   double *scal = nullptr;   // [4]: Q, Q2, max abs(q), spare
   double *qpart = nullptr;  // [4*nblk] per counting block: sum q, sum q^2, max abs(q), charged count
-  double *eslot = nullptr;  // [2*kESlots] energy sums: reciprocal, then real space
+  double *eslot = nullptr;  // energy partials: [ (Mx/2) My ] reciprocal, then [ncells] real space; blocks
+                            // add into slot block mod kESlots, or in the deterministic mode each block
+                            // writes its own slot (summed in a fixed order)
   void *grid = nullptr;     // real [G]
   void *spec = nullptr;     // complex [G/2]
   void *fspec = nullptr;    // complex [4][G/2]

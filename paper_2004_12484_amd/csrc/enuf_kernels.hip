@@ -604,12 +604,15 @@ __global__ __launch_bounds__(kColW * kColG) void k_sort_colscan(int *__restrict_
 // and charged counts and the charge sums.
 __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, SortPlan sp, int *off_t, int *off_c,
                                                     const double *__restrict__ qpart, double *scal, int *counts,
-                                                    double *eslot, int persist) {
+                                                    double *eslot, size_t eoff, int persist) {
+  // the energy slots the transform and pair kernels add into
+  for (int i = threadIdx.x; i < kESlots; i += blockDim.x) {
+    eslot[i] = 0.0;
+    eslot[eoff + i] = 0.0;
+  }
   // with persistent binning an evaluation that keeps the last sort only
   // reduces the charge sums (from k_refresh's partials)
   const bool sorting = !persist || counts[3] != 0;
-  // the energy slots the transform and pair kernels add into
-  for (int i = threadIdx.x; i < 2 * kESlots; i += blockDim.x) eslot[i] = 0.0;
   // per-block charge sums, loaded first so their latency overlaps the scans
   double a = 0.0, b = 0.0, m = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < sp.nblk; i += blockDim.x) {
@@ -908,6 +911,89 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
 }
 
 // --------------------------------------------------------------------------
+// Deterministic mode: the particles of every bin in caller-index order, so
+// that every later sum (spread columns, pair candidates, energy partials)
+// runs in one order from run to run.  Bins of up to kDetSmall particles are
+// ordered by one thread (insertion sort in place); larger ones are listed
+// (in the dead key array of the order) and ordered by one workgroup each
+// (bitonic sort of (index, position) pairs in LDS, records moved through the
+// dead staging array); a bin above kDetBig sets flag bit 1.
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_det_small(int nbins, const int *__restrict__ off, int *perm,
+                                                      real4<R> *part, int *big, int *nbig, const int *need) {
+  if (need && *need == 0) return;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbins; b += gridDim.x * blockDim.x) {
+    const int s0 = off[b], n = off[b + 1] - s0;
+    if (n < 2) continue;
+    if (n > kDetSmall) {
+      big[atomicAdd(nbig, 1)] = b;
+      continue;
+    }
+    for (int i = 1; i < n; ++i) {
+      const int key = perm[s0 + i];
+      const real4<R> rec = part[s0 + i];
+      int j = i - 1;
+      while (j >= 0 && perm[s0 + j] > key) {
+        perm[s0 + j + 1] = perm[s0 + j];
+        part[s0 + j + 1] = part[s0 + j];
+        --j;
+      }
+      perm[s0 + j + 1] = key;
+      part[s0 + j + 1] = rec;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_det_big(const int *__restrict__ off, int *perm, real4<R> *part,
+                                                    real4<R> *tmp, const int *__restrict__ big,
+                                                    const int *__restrict__ nbig, int *counts, const int *need) {
+  if (need && *need == 0) return;
+  __shared__ int key[kDetBig], pos[kDetBig];
+  const int nb = *nbig;
+  for (int k = blockIdx.x; k < nb; k += gridDim.x) {
+    const int b = big[k];
+    const int s0 = off[b], n = off[b + 1] - s0;
+    if (n > kDetBig) {
+      if (threadIdx.x == 0) atomicOr(&counts[2], 2);
+      continue;
+    }
+    int m = 1;
+    while (m < n) m <<= 1;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      key[i] = i < n ? perm[s0 + i] : 0x7fffffff;
+      pos[i] = i;
+      if (i < n) tmp[s0 + i] = part[s0 + i];
+    }
+    __syncthreads();
+    for (int size = 2; size <= m; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const bool up = (i & size) == 0;
+            const int ki = key[i], kj = key[j];
+            if ((ki > kj) == up) {
+              key[i] = kj;
+              key[j] = ki;
+              const int t = pos[i];
+              pos[i] = pos[j];
+              pos[j] = t;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      perm[s0 + i] = key[i];
+      part[s0 + i] = tmp[s0 + pos[i]];
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
 // spread: rho_l = sum_i q_i B(s_i - l)   (type-1 gridding, Eq. 36)
 //
 // One workgroup owns one grid tile of T_x*T_y*T_z points and accumulates it in
@@ -990,20 +1076,20 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
   R *my = acc[wv];
 
   for (int base = 0; base < total; base += blockDim.x) {
-    if (tid == 0) nstaged = 0;
-    __syncthreads();
     const int c = base + tid;
+    real4<R> v{};
+    int ls[3] = {0, 0, 0}, cnt[3] = {0, 0, 0}, js[3] = {0, 0, 0};
+    R fr[3] = {R(0), R(0), R(0)};
+    bool hit = false;
     if (c < total) {
       int lo = 0, hi = nruns;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (rpre[mid] <= c) lo = mid; else hi = mid;
       }
-      const real4<R> v = part[rstart[lo] + (c - rpre[lo])];
+      v = part[rstart[lo] + (c - rpre[lo])];
       const R s[3] = {v.x, v.y, v.z};
-      int ls[3], cnt[3], js[3];
-      R fr[3];
-      bool hit = true;
+      hit = true;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const R fl = floor(s[d]);
@@ -1024,8 +1110,14 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
         }
         hit = hit && cnt[d] > 0;
       }
+    }
+    {
+      // staging slots in candidate order (a block scan, so the order of the
+      // sums is the same from run to run)
+      int ns;
+      const int slot = block_exscan_int(hit ? 1 : 0, &ns);
+      if (tid == 0) nstaged = ns;
       if (hit) {
-        const int slot = atomicAdd(&nstaged, 1);
         // loop over the shorter of z and x; lanes cover the other two axes
         const bool loopz = cnt[2] <= cnt[0];
         const int aA = loopz ? 1 : 2, aB = loopz ? 0 : 1, aC = loopz ? 2 : 0;
@@ -1668,7 +1760,11 @@ __global__ __launch_bounds__(kBlock) void k_z_psi(const Cx<R> *__restrict__ spec
     }
   }
   const double tot = block_sum(en);
-  if (threadIdx.x == 0) atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+  // deterministic mode: one slot per block, summed in a fixed order
+  if (threadIdx.x == 0) {
+    if (g.det) eslot[blockIdx.x] = tot;
+    else atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+  }
 }
 
 // z pass fused with the scaling and influence steps.  For each pencil
@@ -1736,7 +1832,11 @@ __global__ __launch_bounds__(kBlock) void k_z_fused(const Cx<R> *__restrict__ sp
     __syncthreads();
   }
   const double tot = block_sum(en);
-  if (threadIdx.x == 0) atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+  // deterministic mode: one slot per block, summed in a fixed order
+  if (threadIdx.x == 0) {
+    if (g.det) eslot[blockIdx.x] = tot;
+    else atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+  }
 }
 
 // x pass, inverse, nf components: bins 0 .. Mx/2-1 of each field (Nyquist
@@ -2490,7 +2590,11 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
   }
   if (MODE == 0) {
     const double tot = block_sum(e);
-    if (tid == 0) atomicAdd(&eslot[kESlots + blockIdx.x % kESlots], tot);
+    // deterministic mode: one slot per cell, summed in a fixed order
+    if (tid == 0) {
+      if (g.det) eslot[blockIdx.x] = tot;
+      else atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+    }
   }
 }
 
@@ -2758,7 +2862,7 @@ __global__ __launch_bounds__(256) void k_init_ws(Geom g, TabOff t, R *__restrict
     counts[4] = -1;  // no all-active flag seen yet
   }
   if (blockIdx.x == 0)
-    for (int j = threadIdx.x; j < 2 * kESlots; j += blockDim.x) eslot[j] = 0.0;
+    (void)eslot;
 }
 
 hipError_t launch_init_ws(const Geom &g, const Work &w, hipStream_t st, bool fp64) {
@@ -2917,7 +3021,7 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   hipLaunchKernelGGL(k_sort_colscan, dim3((nbk + kColW - 1) / kColW), dim3(kColW * kColG), 0, st, w.hist, sp,
                      w.bbase, need);
   hipLaunchKernelGGL(k_sort_base, dim3(1), dim3(1024), 0, st, w.bbase, sp, w.off_t, w.off_c,
-                     (const double *)w.qpart, w.scal, w.counts, w.eslot, persist ? 1 : 0);
+                     (const double *)w.qpart, w.scal, w.counts, w.eslot, eslot_real_off(g), persist ? 1 : 0);
   hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
                      x, q, g, sp, (const int *)w.key_t, (const int *)w.key_c, (const int *)w.hist,
                      (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c, need);
@@ -2925,6 +3029,23 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
                      (const real4<R> *)w.stg_t, (const int2 *)w.ik_t, w.key_t, (const real4<R> *)w.stg_c,
                      (const int2 *)w.ik_c, w.key_c, (real4<R> *)w.part_t, w.perm_t, w.off_t,
                      (real4<R> *)w.part_c, w.perm_c, w.off_c, need);
+  if (g.det) {
+    // bins in caller-index order; the key arrays (dead after the sort) hold
+    // the lists of large bins, the staging arrays the moved records
+    const int nbin[2] = {sp.nbins[0], sp.nbins[1]};
+    int *perms[2] = {w.perm_t, w.perm_c};
+    const int *offs[2] = {w.off_t, w.off_c};
+    real4<R> *parts[2] = {(real4<R> *)w.part_t, (real4<R> *)w.part_c};
+    real4<R> *tmps[2] = {(real4<R> *)w.stg_t, (real4<R> *)w.stg_c};
+    int *bigs[2] = {w.key_t, w.key_c};
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.counts + 6, 2, 0);
+    for (int o = 0; o < 2; ++o) {
+      hipLaunchKernelGGL((k_det_small<R>), dim3(std::min(4096, (nbin[o] + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                         st, nbin[o], offs[o], perms[o], parts[o], bigs[o], w.counts + 6 + o, need);
+      hipLaunchKernelGGL((k_det_big<R>), dim3(256), dim3(kBlock), 0, st, offs[o], perms[o], parts[o], tmps[o],
+                         (const int *)bigs[o], (const int *)(w.counts + 6 + o), w.counts, need);
+    }
+  }
   ENUF_TRY(hipGetLastError());
   mark(2);
   // spread
@@ -2940,7 +3061,9 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   mark(4);
   // z fused: forward z, influence, energy, inverse z of the field spectra
   const int zp = hx * g.M[1];
-  if (analytic && sizeof(R) == 4 && (P.lnz == 7 || P.lnz == 8) && zp % 16 == 0)
+  const bool zpsi = analytic && sizeof(R) == 4 && (P.lnz == 7 || P.lnz == 8) && zp % 16 == 0;
+  const int nzb = zpsi ? zp / 16 : P.zblocks;  // z-pass blocks: one energy partial each
+  if (zpsi)
     hipLaunchKernelGGL((k_z_psi<R>), dim3(zp / 16), dim3(kBlock), (size_t)16 * sizeof(Cx<R>) << P.lnz, st,
                        (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, P.lnz, P.lhx, tw_z, sx, sy, sz, kvx, kvy, kvz,
                        w.eslot);
@@ -2973,14 +3096,15 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   // pair
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 0, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.eslot);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.eslot + eslot_real_off(g));
   else
     hipLaunchKernelGGL((k_pair<R, 0, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.eslot);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), R(1), F, phi, w.eslot + eslot_real_off(g));
   ENUF_TRY(hipGetLastError());
   mark(8);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, (const double *)w.eslot, kESlots,
-                     (const double *)(w.eslot + kESlots), kESlots, (const double *)w.scal, g, E, w.counts);
+  const int nks = g.det ? nzb : kESlots, nrs = g.det ? g.ncells : kESlots;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(g.det ? 1024 : 64), 0, st, (const double *)w.eslot, nks,
+                     (const double *)(w.eslot + eslot_real_off(g)), nrs, (const double *)w.scal, g, E, w.counts);
   ENUF_TRY(hipGetLastError());
   mark(9);
   return hipSuccess;
@@ -2999,10 +3123,12 @@ hipError_t launch_adjoint(const Geom &g, const Work &w, hipStream_t st, double g
   ENUF_TRY(hipGetLastError());
   if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
     hipLaunchKernelGGL((k_pair<R, 1, true>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.eslot);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq,
+                       w.eslot + eslot_real_off(g));
   else
     hipLaunchKernelGGL((k_pair<R, 1, false>), dim3(g.ncells), dim3(kPairBlock), 0, st, (const real4<R> *)w.part_c,
-                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq, w.eslot);
+                       w.perm_c, w.off_c, g, w.scal, pair_const<R>(g), (R)gscale, dEdx, dEdq,
+                       w.eslot + eslot_real_off(g));
   ENUF_TRY(hipGetLastError());
   if (gdev) {
     if (dEdx) hipLaunchKernelGGL((k_scale_dev<R>), dim3(256), dim3(kBlock), 0, st, dEdx, 3LL * g.n, gdev);

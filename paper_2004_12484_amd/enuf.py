@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libenuf.so")
 ENUF_OK, ENUF_EINVAL, ENUF_ENOMEM, ENUF_EDEVICE, ENUF_ENONFINITE, ENUF_ESTATE, ENUF_EUNSUPPORTED = range(7)
 ENUF_FP64, ENUF_FP32 = 0, 1
 (OPT_KE, OPT_TIMING, OPT_GRAPH, OPT_CHECK, OPT_FORCE_MODE, OPT_SLATER, OPT_WINDOW, OPT_OVERSAMPLING,
- OPT_SKIN, OPT_SPREAD_F16) = range(10)
+ OPT_SKIN, OPT_SPREAD_F16, OPT_DETERMINISTIC) = range(11)
 WINDOWS = {"bspline": 0, "gaussian": 1}
 FORCE_MODES = {"ik": 0, "analytic": 1}
 STAGE_GRID, STAGE_SPECTRUM, STAGE_FIELDS, STAGE_SORTED, STAGE_COUNTS, STAGE_CELLS = range(6)
