@@ -213,6 +213,49 @@ def test_dense_pair_search_many_chunks_vs_mirror(prec):
     _compare(out, m, prec)
 
 
+# Uneven pair-search loads: a long box (26 x 6 x 6 cells) with a dense clump
+# whose neighbourhood fills many LDS staging chunks next to cells with a
+# handful of candidates, and cells with more active particles than lanes
+# (mostly neutral, potentials requested: several lane batches per cell);
+# the adjoint goes through the same kernels.
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_long_box_with_clump_vs_mirror(prec):
+    rng = np.random.default_rng(71)
+    box = np.array([40.0, 9.0, 9.0])   # r_c = 1.5: 26 x 6 x 6 cells
+    x = rng.uniform(0, 1, (3240, 3)) * box
+    clump = np.array([20.3, 4.1, 7.9]) + rng.uniform(-0.7, 0.7, (1600, 3))   # ~1300 charges in 1-8 cells
+    x = np.concatenate([x, clump])
+    n = len(x)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0) * rng.uniform(0.5, 1.5, n)
+    q[rng.uniform(size=n) < 0.2] = 0.0
+    eng, out = run(x, q, box, 2.0, 1.5, (64, 16, 16), 4, precision=prec)
+    xr, qr = _as_precision(x, q, prec)
+    m = em.enuf(xr, qr, box, 2.0, 1.5, (64, 16, 16), 4)
+    _compare(out, m, prec)
+    gx, gq = eng.energy_grad(1.0)
+    tol = TOL64_F if prec == "f64" else TOL32_F
+    assert rms_rel(gx.double().cpu().numpy(), m["grad_x"]) <= tol
+    assert rms_rel(gq.double().cpu().numpy(), m["phi"]) <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_many_home_particles_vs_mirror(prec):
+    # 60 particles per unit volume, 97% neutral: ~200 active particles per
+    # cell (two lane batches of 192) but few charged candidates
+    rng = np.random.default_rng(72)
+    box = np.array([12.0, 6.0, 6.0])
+    n = int(60 * box.prod())
+    x = rng.uniform(0, 1, (n, 3)) * box
+    q = np.zeros(n)
+    sel = rng.permutation(n)[: (n * 3 // 100) // 2 * 2]
+    q[sel[: len(sel) // 2]] = 1.0
+    q[sel[len(sel) // 2:]] = -1.0
+    eng, out = run(x, q, box, 2.0, 1.5, (32, 16, 16), 4, precision=prec)
+    xr, qr = _as_precision(x, q, prec)
+    m = em.enuf(xr, qr, box, 2.0, 1.5, (32, 16, 16), 4, want_grad=False)
+    _compare(out, m, prec)
+
+
 # ---------------------------------------------------------------- edges
 def test_single_charge_wigner():
     L = 5.0
