@@ -2025,6 +2025,22 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(const real4<R> *__restr
   }
 }
 
+// Staged rows of the tile gather start at the 16-byte boundary at or below
+// the region's first point: xoff points before it (tiles start at multiples
+// of 4 points, so xoff is the same for every block), and the row pitch W is
+// the region's width T_x + P - 1 + 2 D plus xoff, rounded up to whole chunks.
+template <typename FT, int P>
+__host__ __device__ __forceinline__ int gather_xoff(int D0) {
+  constexpr int PC = sizeof(FT) <= 16 ? 16 / (int)sizeof(FT) : 1;
+  return (PC - (P / 2 - 1 + D0) % PC) % PC;
+}
+template <typename FT, int P>
+__host__ __device__ __forceinline__ int gather_pitch(const Geom &g) {
+  constexpr int PC = sizeof(FT) <= 16 ? 16 / (int)sizeof(FT) : 1;
+  const int e = gather_xoff<FT, P>(g.sdig[0]) + g.T[0] + P - 1 + 2 * g.sdig[0];
+  return (e + PC - 1) / PC * PC;
+}
+
 // Tile form of the gather: one workgroup per SY x SZ spread tiles stages
 // their fields plus the (P-1)-point halo in LDS, then interpolates every
 // active particle of those tiles from LDS.  Four lanes share a particle: each sums the (z, y) rows of
@@ -2070,48 +2086,48 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
   // with persistent binning a particle may sit up to sdig points outside its
   // tile: the region grows by that margin on each side
   const int D0 = g.sdig[0], D1 = g.sdig[1], D2 = g.sdig[2];
-  const int E0 = g.T[0] + P - 1 + 2 * D0, E1 = nys * g.T[1] + P - 1 + 2 * D1, E2 = nzs * g.T[2] + P - 1 + 2 * D2;
+  const int E1 = nys * g.T[1] + P - 1 + 2 * D1, E2 = nzs * g.T[2] + P - 1 + 2 * D2;
   const int e0x = t0[0] - P / 2 + 1 - D0, e0y = t0[1] - P / 2 + 1 - D1, e0z = t0[2] - P / 2 + 1 - D2;
   const int span[3] = {g.T[0], nys * g.T[1], nzs * g.T[2]};
   const int marg[3] = {D0, D1, D2};
+  // The block's region plus halo goes to LDS by direct loads (global memory
+  // to LDS, no registers): rows of W points starting at the 16-byte boundary
+  // at or below the region's first x (xoff points before it), so that every
+  // 16-byte chunk of a row is one aligned load; all of a lane's loads are in
+  // flight at once.  A wave's loads land in 64 consecutive chunks, chunk c of
+  // the block at byte 16 c.
+  // grid points per chunk, chunks per grid point (one of them is 1)
+  constexpr int PC = sizeof(FT) <= 16 ? 16 / (int)sizeof(FT) : 1;
+  constexpr int CPP = sizeof(FT) <= 16 ? 1 : (int)sizeof(FT) / 16;
+  const int xoff = gather_xoff<FT, P>(D0), W = gather_pitch<FT, P>(g);
   {
-    // the block's region plus halo, as one flat index over (z, y, x): eight
-    // loads in flight per lane before any is written to LDS; no wrapping
-    // arithmetic when the region lies inside the grid
-    constexpr int kB = 8;
-    const int E01 = E0 * E1, nel = E01 * E2;
-    const float i01 = 1.0f / (float)E01, i0 = 1.0f / (float)E0;
-    const bool inner = e0x >= 0 && e0y >= 0 && e0z >= 0 && e0x + E0 <= g.M[0] && e0y + E1 <= g.M[1] &&
+    const int WC = W * CPP / PC, nch = WC * E1 * E2;
+    const int xa = e0x - xoff;  // a multiple of PC: tiles start at multiples of 4 points
+    const bool inner = xa >= 0 && e0y >= 0 && e0z >= 0 && xa + W <= g.M[0] && e0y + E1 <= g.M[1] &&
                        e0z + E2 <= g.M[2];
-    using V = pod_t<FT>;
-    const V *fsrc = reinterpret_cast<const V *>(field);
-    V *edst = reinterpret_cast<V *>(ext);
-    for (int eb = tid; eb < nel; eb += kB * blockDim.x) {
-      V v[kB];
-#pragma unroll
-      for (int k = 0; k < kB; ++k) {
-        const int e = eb + k * blockDim.x;
-        v[k] = V{};
-        if (e < nel) {
-          const int iz = (int)(((float)e + 0.5f) * i01);
-          const int rem = e - iz * E01;
-          const int iy = (int)(((float)rem + 0.5f) * i0);
-          const int ix = rem - iy * E0;
-          int gx = e0x + ix, gy = e0y + iy, gz = e0z + iz;
-          if (!inner) {
-            gx = wrapi(gx, g.M[0]);
-            gy = wrapi(gy, g.M[1]);
-            gz = wrapi(gz, g.M[2]);
-          }
-          v[k] = fsrc[((size_t)gz * g.M[1] + gy) * g.M[0] + gx];
+    const float iwc = 1.0f / (float)WC, ie1 = 1.0f / (float)E1;
+    unsigned char *lds = smem_raw;
+    for (int c0 = 0; c0 < nch; c0 += blockDim.x) {
+      const int wbase = c0 + (tid & ~63);
+      const int c = wbase + (tid & 63);
+      if (c < nch) {
+        const int row = (int)(((float)c + 0.5f) * iwc);
+        const int cx = c - row * WC;
+        const int iz = (int)(((float)row + 0.5f) * ie1);
+        const int iy = row - iz * E1;
+        int gx = xa + cx * PC / CPP, gy = e0y + iy, gz = e0z + iz;
+        if (!inner) {
+          gx = wrapi(gx, g.M[0]);
+          gy = wrapi(gy, g.M[1]);
+          gz = wrapi(gz, g.M[2]);
         }
-      }
-#pragma unroll
-      for (int k = 0; k < kB; ++k) {
-        const int e = eb + k * blockDim.x;
-        if (e < nel) edst[e] = v[k];
+        const unsigned char *src = reinterpret_cast<const unsigned char *>(
+                                       field + ((size_t)gz * g.M[1] + gy) * g.M[0] + gx) + 16 * (cx % CPP);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)(lds + 16 * wbase), 16, 0, 0);
       }
     }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every chunk has landed
   }
   __syncthreads();
   // the block's particles: the sorted ranges of its spread tiles, end to end
@@ -2185,7 +2201,7 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       mwy[m] = YS == 2 ? pick(yb, wy[2 * m], wy[2 * m + 1]) : wy[m];
       if (GRAD) mdy[m] = YS == 2 ? pick(yb, dy[2 * m], dy[2 * m + 1]) : dy[m];
     }
-    const FT *base = ext + ((l[2] + za) * E1 + l[1] + yb) * E0 + l[0];
+    const FT *base = ext + ((l[2] + za) * E1 + l[1] + yb) * W + l[0] + xoff;
 #pragma unroll
     for (int mz = 0; mz < ZN; ++mz) {
       // gradient form: per z plane, y sums of the row sums (sum_y w_y sw,
@@ -2193,7 +2209,7 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
       R tw = 0, tdy = 0, td = 0;
 #pragma unroll
       for (int my = 0; my < YN; ++my) {
-        const FT *row = base + (ZS * mz * E1 + YS * my) * E0;
+        const FT *row = base + (ZS * mz * E1 + YS * my) * W;
         // x sums of the row first, then the row's z-y weight
         if constexpr (!GRAD) {
           R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -2908,7 +2924,7 @@ static void launch_spread(const Geom &g, const Work &w, hipStream_t st) {
 }
 template <typename FT, int P>
 static size_t gather_tile_lds(const Geom &g, int sy, int sz) {
-  return (size_t)(g.T[0] + P - 1 + 2 * g.sdig[0]) * (sy * g.T[1] + P - 1 + 2 * g.sdig[1]) *
+  return (size_t)gather_pitch<FT, P>(g) * (sy * g.T[1] + P - 1 + 2 * g.sdig[1]) *
          (sz * g.T[2] + P - 1 + 2 * g.sdig[2]) * sizeof(FT);
 }
 // Gather kinds: ik forces and potentials from the interleaved (E, psi) grid;
