@@ -27,6 +27,7 @@ constexpr int kSortBuckets = 256;    // target buckets per order
 constexpr int kSortBucketsMax = 4096; // cap on the target for large systems (LDS of the count pass)
 constexpr int kSortFineLog = 12;     // at most 2^12 keys per bucket
 constexpr int kSortChunkMax = 2048;  // particles grouped in LDS at a time by the staging pass
+constexpr int kSortStageBlock = 1024;  // threads per block of the staging pass
 constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass
 constexpr int kSortFineRegs = 8;     // particles per thread held in registers by the fine pass
 constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)

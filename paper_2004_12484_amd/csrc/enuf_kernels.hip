@@ -683,7 +683,7 @@ __global__ __launch_bounds__(1024) void k_sort_base(int *__restrict__ bbase, Sor
 // Staged records: (s_x, s_y, s_z, q) for the tile order, (x_w, y_w, z_w, q)
 // for the cell order, each with (source index, key).
 template <typename R>
-__global__ __launch_bounds__(kSortBlock) void k_sort_stage(const R *__restrict__ x, const R *__restrict__ q, Geom g,
+__global__ __launch_bounds__(kSortStageBlock) void k_sort_stage(const R *__restrict__ x, const R *__restrict__ q, Geom g,
                                                            SortPlan sp, const int *__restrict__ key_t,
                                                            const int *__restrict__ key_c,
                                                            const int *__restrict__ hist,
@@ -691,7 +691,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_stage(const R *__restrict__
                                                            int2 *ik_t, real4<R> *stg_c, int2 *ik_c,
                                                            const int *need) {
   if (need && *need == 0) return;
-  constexpr int U = kSortChunkMax / kSortBlock;
+  constexpr int U = kSortChunkMax / kSortStageBlock;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int nbk = sp.nb[0] + sp.nb[1];
   const int nbm = max(sp.nb[0], sp.nb[1]);
@@ -738,8 +738,8 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_stage(const R *__restrict__
       int kk[U], rr[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = c0 + u * kSortBlock + tid;
-        kk[u] = (u * kSortBlock < sp.chunk && i < i1) ? key[i] : -1;
+        const int i = c0 + u * kSortStageBlock + tid;
+        kk[u] = (u * kSortStageBlock + tid < sp.chunk && i < i1) ? key[i] : -1;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) rr[u] = kk[u] >= 0 ? atomicAdd(&cnt[kk[u] >> sh], 1) : 0;
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_stage(const R *__restrict__
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (kk[u] < 0) continue;
-        const int i = c0 + u * kSortBlock + tid;
+        const int i = c0 + u * kSortStageBlock + tid;
         const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
         R xw[3], sg[3];
         particle_coords(p3, g, xw, sg);
@@ -3038,7 +3038,7 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
                      w.bbase, need);
   hipLaunchKernelGGL(k_sort_base, dim3(1), dim3(1024), 0, st, w.bbase, sp, w.off_t, w.off_c,
                      (const double *)w.qpart, w.scal, w.counts, w.eslot, eslot_real_off(g), persist ? 1 : 0);
-  hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
+  hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortStageBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
                      x, q, g, sp, (const int *)w.key_t, (const int *)w.key_c, (const int *)w.hist,
                      (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c, need);
   hipLaunchKernelGGL((k_sort_fine<R>), dim3(nbk), dim3(kSortFineBlock), lds_fine, st, sp, (const int *)w.bbase,
