@@ -1673,6 +1673,139 @@ __device__ __forceinline__ void fft_stage_ip(int ln, int lns, int lnb, const Cx<
 // the spectrum throughout (stages in place), so a block reads and writes
 // 128-byte rows and every thread owns a butterfly.  Same results as
 // k_z_fused with nf = 1, fbase = 3.
+// One in-place Stockham stage (radix RAD, span 2^lns) over a 2^ln-point
+// transform of 2^lnb pencils held in X, with PER butterflies per thread: all
+// of a thread's inputs are read, the block waits, then the outputs are
+// written.
+template <typename R, int RAD, int DIR, int PER>
+__device__ __forceinline__ void fft_stage_ip_n(int ln, int lns, int lnb, const Cx<R> *__restrict__ tw, Cx<R> *X) {
+  constexpr int LR = RAD == 16 ? 4 : (RAD == 8 ? 3 : (RAD == 4 ? 2 : 1));
+  const int lq = ln - LR;
+  const int lt = ln - lns - LR;
+  Cx<R> v[PER][RAD];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int w = threadIdx.x + i * blockDim.x;
+    const int f = w & ((1 << lnb) - 1);
+    const int j = (w >> lnb) & ((1 << lq) - 1);
+    const int k = j & ((1 << lns) - 1);
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[i][r] = X[((j + (r << lq)) << lnb) + f];
+    if (lns > 0) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        Cx<R> wr = tw[(r * k) << lt];
+        if (DIR > 0) wr = cconj(wr);
+        v[i][r] = cmul(v[i][r], wr);
+      }
+    }
+    if constexpr (RAD == 2) {
+      const Cx<R> a = v[i][0], b = v[i][1];
+      v[i][0] = cadd(a, b);
+      v[i][1] = csub(a, b);
+    } else {
+      dft<R, RAD, DIR>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int w = threadIdx.x + i * blockDim.x;
+    const int f = w & ((1 << lnb) - 1);
+    const int j = (w >> lnb) & ((1 << lq) - 1);
+    const int k = j & ((1 << lns) - 1);
+    const int ob = ((j - k) << LR) + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) X[((ob + (r << lns)) << lnb) + f] = v[i][r];
+  }
+}
+
+// The z pass of the potential spectrum alone for 512-point z axes (FP32,
+// analytic forces): 16 pencils per block in one 64 KB LDS buffer, 512
+// threads; forward stages of radix 16, 16, 2 (the first reads global memory
+// in rows of 16 pencils), the influence multiply and the energy partial, and
+// inverse stages of radix 2, 16, 16 (the last writes global memory).  The
+// block's energy partial is reduced through the same buffer once it is
+// free, so the block needs no other LDS.
+template <typename R>
+__global__ __launch_bounds__(512) void k_z_psi512(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec,
+                                                  Geom g, int lhx, const Cx<R> *__restrict__ tw_z,
+                                                  const R *__restrict__ sx, const R *__restrict__ sy,
+                                                  const R *__restrict__ sz, const R *__restrict__ kvx,
+                                                  const R *__restrict__ kvy, const R *__restrict__ kvz,
+                                                  double *eslot) {
+  constexpr int lnz = 9, n = 512, lnb = 4, nb = 16;
+  extern __shared__ unsigned char smem_raw[];
+  Cx<R> *X = reinterpret_cast<Cx<R> *>(smem_raw);
+  const int hx = 1 << lhx;
+  const size_t inner = (size_t)hx * g.M[1];
+  const size_t p0 = (size_t)blockIdx.x << lnb;
+  const int tid = threadIdx.x;
+  const int f = tid & (nb - 1), j = tid >> lnb;  // pencil, butterfly (0..31) of a radix-16 stage
+  // forward: radix 16 (span 1) from global memory
+  {
+    Cx<R> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = spec[(size_t)(j + (r << 5)) * inner + p0 + f];
+    dft<R, 16, -1>(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[((j * 16 + r) << lnb) + f] = v[r];
+  }
+  __syncthreads();
+  fft_stage_ip_n<R, 16, -1, 1>(lnz, 4, lnb, tw_z, X);
+  __syncthreads();
+  fft_stage_ip_n<R, 2, -1, 8>(lnz, 8, lnb, tw_z, X);
+  __syncthreads();
+  double en = 0.0;
+  {
+    const int pidx = (int)p0 + f;
+    const int kx = pidx & (hx - 1), ky = pidx >> lhx;
+    const R kxy2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky];
+    const R sxy = sx[kx] * sy[ky];
+    const R wk = kx > 0 ? R(2) : R(1);
+    for (int kz = tid >> lnb; kz < n; kz += blockDim.x >> lnb) {
+      const int e = (kz << lnb) + f;
+      const R k2 = kxy2 + kvz[kz] * kvz[kz];
+      const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
+      const Cx<R> r = X[e];
+      en += (double)(wk * gv * (r.x * r.x + r.y * r.y));
+      X[e] = Cx<R>{gv * r.x, gv * r.y};
+    }
+  }
+  __syncthreads();
+  // inverse: radix 2 (span 1) and radix 16 (span 2) in place
+  fft_stage_ip_n<R, 2, 1, 8>(lnz, 0, lnb, tw_z, X);
+  __syncthreads();
+  fft_stage_ip_n<R, 16, 1, 1>(lnz, 1, lnb, tw_z, X);
+  __syncthreads();
+  // last stage: radix 16, span 32, to global memory
+  {
+    const int k = j & 31;
+    const int ob = ((j - k) << 4) + k;
+    Cx<R> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = X[((j + (r << 5)) << lnb) + f];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], cconj(tw_z[r * k]));
+    dft<R, 16, 1>(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) fspec[(size_t)(ob + (r << 5)) * inner + p0 + f] = v[r];
+  }
+  // energy partial: wave sums, then the waves' sums through the freed buffer
+  en = wave_sum(en);
+  __syncthreads();  // every thread has read X
+  double *red = reinterpret_cast<double *>(smem_raw);
+  if ((tid & 63) == 0) red[tid >> 6] = en;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += red[k];
+    // deterministic mode: one slot per block, summed in a fixed order
+    if (g.det) eslot[blockIdx.x] = tot;
+    else atomicAdd(&eslot[blockIdx.x % kESlots], tot);
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_z_psi(const Cx<R> *__restrict__ spec, Cx<R> *__restrict__ fspec, Geom g,
                                                   int lnz, int lhx, const Cx<R> *__restrict__ tw_z,
@@ -3077,9 +3210,12 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   mark(4);
   // z fused: forward z, influence, energy, inverse z of the field spectra
   const int zp = hx * g.M[1];
-  const bool zpsi = analytic && sizeof(R) == 4 && (P.lnz == 7 || P.lnz == 8) && zp % 16 == 0;
+  const bool zpsi = analytic && sizeof(R) == 4 && (P.lnz == 7 || P.lnz == 8 || P.lnz == 9) && zp % 16 == 0;
   const int nzb = zpsi ? zp / 16 : P.zblocks;  // z-pass blocks: one energy partial each
-  if (zpsi)
+  if (zpsi && P.lnz == 9)
+    hipLaunchKernelGGL((k_z_psi512<R>), dim3(zp / 16), dim3(512), (size_t)16 * sizeof(Cx<R>) << 9, st,
+                       (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, P.lhx, tw_z, sx, sy, sz, kvx, kvy, kvz, w.eslot);
+  else if (zpsi)
     hipLaunchKernelGGL((k_z_psi<R>), dim3(zp / 16), dim3(kBlock), (size_t)16 * sizeof(Cx<R>) << P.lnz, st,
                        (const Cx<R> *)w.spec, (Cx<R> *)w.fspec, g, P.lnz, P.lhx, tw_z, sx, sy, sz, kvx, kvy, kvz,
                        w.eslot);

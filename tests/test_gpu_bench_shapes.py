@@ -78,11 +78,11 @@ def _check_results(out, m, F_ref):
     assert np.abs(out["F"] - F_ref).max() <= 20 * TOL32_F * np.abs(F_ref).max()
 
 
-@pytest.mark.parametrize("M", [(16, 16, 128), (16, 16, 256), (32, 16, 128)])
+@pytest.mark.parametrize("M", [(16, 16, 128), (16, 16, 256), (32, 16, 128), (16, 16, 512)])
 def test_analytic_f32_potential_z_pass_vs_mirror(M):
-    """FP32 analytic forces with a 128- or 256-point z axis: the z pass of the
-    potential spectrum alone; psi grid, energies, forces (minus the mirror's
-    exact gradient) and potentials."""
+    """FP32 analytic forces with a 128-, 256- or 512-point z axis: the z pass
+    of the potential spectrum alone; psi grid, energies, forces (minus the
+    mirror's exact gradient) and potentials."""
     box = (7.0, 7.5, 0.45 * M[2])
     x, q, box = _system(1200, box, seed=M[2] + M[0], neutral_every=9)
     alpha, rc, p = 1.25, 3.2, 6
