@@ -757,18 +757,28 @@ __global__ __launch_bounds__(kSortStageBlock) void k_sort_stage(const R *__restr
         run += v;
       }
       __syncthreads();
+      // positions and charges of the U particles, loaded together (a lane
+      // without a particle rereads the chunk's first one)
+      R px[U][3], pq[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = kk[u] >= 0 ? c0 + u * kSortStageBlock + tid : c0;
+        px[u][0] = x[3 * i];
+        px[u][1] = x[3 * i + 1];
+        px[u][2] = x[3 * i + 2];
+        pq[u] = q[i];
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (kk[u] < 0) continue;
         const int i = c0 + u * kSortStageBlock + tid;
-        const R p3[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
         R xw[3], sg[3];
-        particle_coords(p3, g, xw, sg);
+        particle_coords(px[u], g, xw, sg);
         real4<R> a;
         a.x = o == 0 ? sg[0] : xw[0];
         a.y = o == 0 ? sg[1] : xw[1];
         a.z = o == 0 ? sg[2] : xw[2];
-        a.w = q[i];
+        a.w = pq[u];
         const int p = cnt[kk[u] >> sh] + rr[u];
         rec[p] = a;
         rik[p] = make_int2(i, kk[u]);
@@ -830,10 +840,15 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
   __syncthreads();
   int kk[U], rr[U];
   if (small) {
+    // every lane loads U keys (past the end: the bucket's last one again),
+    // so the loads go out together instead of one per branch
+    int raw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) raw[u] = e > s ? ik[min(s + u * nt + tid, e - 1)].y : 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = s + u * nt + tid;
-      kk[u] = j < e ? ik[j].y - k0 : -1;
+      kk[u] = j < e ? raw[u] - k0 : -1;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) rr[u] = (unsigned)kk[u] < (unsigned)nf ? atomicAdd(&bin[kk[u]], 1) : 0;
@@ -881,11 +896,13 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
         jj[u] = (unsigned)v < (unsigned)(e - s) ? s + v : -1;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (jj[u] >= 0) {
-          a[u] = *reinterpret_cast<const pod_t<real4<R>> *>(stg + jj[u]);
-          pv[u] = ik[jj[u]].x;
-        }
+      for (int u = 0; u < 4; ++u) {
+        // unconditional loads (a lane past the end rereads the bucket's
+        // first record), all in flight together
+        const int jc = jj[u] >= 0 ? jj[u] : s;
+        a[u] = *reinterpret_cast<const pod_t<real4<R>> *>(stg + jc);
+        pv[u] = ik[jc].x;
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (jj[u] >= 0) {
