@@ -2643,14 +2643,28 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
         if (r < 27) {
           const int a0 = max(0, c0 - rp[r]), a1 = min(rp[r + 1] - rp[r], c0 + nc - rp[r]);
           const R sx = rsh[r][0], sy = rsh[r][1], sz = rsh[r][2];
-          for (int k = a0 + j0; k < a1; k += TS) {
-            const pod_t<real4<R>> v = *reinterpret_cast<const pod_t<real4<R>> *>(part + rs[r] + k);
-            real4<R> u;
-            u.x = v[0] + sx;
-            u.y = v[1] + sy;
-            u.z = v[2] + sz;
-            u.w = v[3];
-            cand[rp[r] + k - c0] = u;
+          // four particles per member at a time, their loads issued together
+          // (past the end a member rereads the first one)
+          constexpr int UB = 4;
+          for (int k0 = a0 + j0; k0 < a1; k0 += UB * TS) {
+            pod_t<real4<R>> v[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+              const int k = k0 + u * TS;
+              v[u] = *reinterpret_cast<const pod_t<real4<R>> *>(part + rs[r] + (k < a1 ? k : a0));
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+              const int k = k0 + u * TS;
+              if (k < a1) {
+                real4<R> w;
+                w.x = v[u][0] + sx;
+                w.y = v[u][1] + sy;
+                w.z = v[u][2] + sz;
+                w.w = v[u][3];
+                cand[rp[r] + k - c0] = w;
+              }
+            }
           }
         }
       }
