@@ -144,6 +144,29 @@ def test_nacl_perfect_lattice_madelung():
     assert np.abs(out["F"]).max() < 1e-6
 
 
+def test_madelung_alpha_trials():
+    """The paper's trial for alpha (Sec. 2.4.2): the Madelung constant of a
+    rock-salt crystal at the ENUF-DPD real-space cutoff r_c = 3 R_c
+    (R_c = 6.954 A) over a range of alpha.  Here 8 x 8 x 8 conventional
+    cells (4096 ions, the paper's ~4000), 64^3 grid, p = 6, FP64: the value
+    is reproduced to 1e-6 from alpha = 0.18 / A up to 0.40 / A, and misses
+    below it (real-space truncation: 5e-3 at 0.10, 6e-4 at 0.12), so the
+    lowest acceptable alpha is the paper's ~0.20 / A."""
+    w = inputs.nacl(cells=8, noise=0.0)
+    rc = 3 * 6.954
+    expect = -(w.N / 2) * 1.747564594633 / (5.64 / 2)
+    rel = {}
+    for a in (0.10, 0.12, 0.15, 0.18, 0.20, 0.25, 0.30, 0.40):
+        eng, out = run(w.x, w.q, w.box, a, rc, (64, 64, 64), 6)
+        rel[a] = abs(out["E"][0] - expect) / abs(expect)
+        assert np.abs(out["F"]).max() < 1e-5
+        eng.close()
+        print(f"alpha={a:.2f}/A: relative Madelung error {rel[a]:.2e}")
+    assert rel[0.10] > 1e-3 and rel[0.12] > 1e-4
+    assert all(rel[a] <= 1e-6 for a in (0.18, 0.20, 0.25, 0.30, 0.40))
+    assert min(a for a in rel if all(rel[b] <= 1e-6 for b in rel if b >= a)) in (0.18, 0.20)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_electrolyte_vs_mirror(prec):
     w = inputs.electrolyte()
