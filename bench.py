@@ -210,6 +210,31 @@ def golden_check(w, F, E, phi=None, name=None):
     return out
 
 
+def copy_probe(dev, mib=1024, reps=10):
+    """Achievable copy bandwidth, the second denominator of the HBM-bound
+    kernels: the library's plain copy kernel over 1 GiB (read + write bytes
+    per second, HIP events around `reps` copies after two warm-ups)."""
+    import torch
+    from paper_2004_12484_amd import enuf
+    nbytes = mib << 20
+    src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        enuf.copy_probe(src, dst)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        enuf.copy_probe(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_copied": nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9,
+            "kernel": "enuf_copy_probe (16 bytes per lane, non-temporal, one workgroup per CU)"}
+
+
 def learned_form(w, target, x, q, args, name, force_mode):
     """The same workload in the same precision at the parameter network's
     setting for `target` (enuf_select_params with the trained network),
@@ -456,6 +481,7 @@ def main():
     ms = ms_total / args.steps
     value = 1000.0 / ms
 
+    copy = copy_probe(dev)
     counts = eng.stage(enuf.STAGE_COUNTS).cpu().numpy()
     nq = int(counts[1])
     Eh = E.cpu().numpy()
@@ -472,7 +498,7 @@ def main():
         achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, dom),
-                "bytes_per_launch": ab[dom]}
+                "bytes_per_launch": ab[dom], "frac_of_copy": achieved / copy["gbs"]}
     else:
         pairs = pair_count(w, nq)
         peak = FP32_VALU_TFLOPS if rs == 4 else FP64_VALU_TFLOPS
@@ -484,7 +510,8 @@ def main():
     # the HBM-bound gates: spread and gather against the HBM peak, with the
     # counter bytes of their kernels beside them when measured on this build
     gates = {k: {"algorithmic_bytes": ab[k], "ms": phases[k], "gbs": hbm[k], "frac": hbm[k] / HBM_PEAK_GBS,
-                 "counter_bytes": measured_traffic(w.name, k)} for k in ("spread", "gather")}
+                 "frac_of_copy": hbm[k] / copy["gbs"], "counter_bytes": measured_traffic(w.name, k)}
+             for k in ("spread", "gather")}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -499,7 +526,7 @@ def main():
         "wall_s": wall, "step_ms": {"median": float(np.median(step_ms)), "p10": float(np.percentile(step_ms, 10)),
                                     "p90": float(np.percentile(step_ms, 90)), "mean": float(step_ms.mean()),
                                     "with_phase_events": ms_phased},
-        "phase_ms": phases, "phase_gbs": hbm, "hbm_gates": gates,
+        "phase_ms": phases, "phase_gbs": hbm, "hbm_gates": gates, "copy_probe": copy,
         "energy": {"total": float(Eh[0]), "real": float(Eh[1]), "recip": float(Eh[2]), "self": float(Eh[3]),
                    "background": float(Eh[4])},
         "accuracy": acc, "roofline": roof,

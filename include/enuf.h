@@ -402,6 +402,16 @@ const char *enuf_last_error(enuf_ctx ctx);
  * never fails). */
 int32_t enuf_device_count(void);
 
+/* enuf_copy_probe -- a plain device-to-device copy of `bytes` bytes from
+ * src to dst (device pointers, 16-byte aligned, bytes a multiple of 16, the
+ * ranges not overlapping) with this library's own kernel, enqueued on
+ * `stream` (NULL: the null stream).  A measurement aid, not part of the
+ * method: the achievable copy bandwidth it shows is the second denominator
+ * the HBM-bound kernels are reported against, beside the published peak.
+ * ENUF_EINVAL for a NULL pointer, misalignment or a bad size; ENUF_EDEVICE
+ * if the launch fails. */
+enuf_status enuf_copy_probe(const void *src, void *dst, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -286,6 +286,18 @@ static hipError_t run_graph(enuf_ctx c, const void *x, const void *q, double *E,
 
 extern "C" {
 
+enuf_status enuf_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
+  if (!src || !dst) return fail(nullptr, ENUF_EINVAL, "src or dst is NULL");
+  if (bytes == 0 || bytes % 16 != 0) return fail(nullptr, ENUF_EINVAL, "bytes must be a positive multiple of 16");
+  if ((uintptr_t)src % 16 != 0 || (uintptr_t)dst % 16 != 0)
+    return fail(nullptr, ENUF_EINVAL, "src and dst must be 16-byte aligned");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return fail(nullptr, ENUF_EINVAL, "src and dst overlap");
+  hipError_t e = enuf::launch_copy16(src, dst, bytes / 16, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "copy probe launch");
+  return ENUF_OK;
+}
+
 int32_t enuf_device_count(void) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) return 0;

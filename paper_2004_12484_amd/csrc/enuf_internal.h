@@ -152,6 +152,9 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
                           double *E, R *F, R *phi, bool all_active, bool want_psi, bool analytic,
                           hipEvent_t *ev);
 
+// Plain device copy of n16 16-byte words (the bandwidth probe).
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, hipStream_t st);
+
 // Adjoint of the last forward: dEdx, dEdq (either may be null).  psi_scalar:
 // the last forward left psi as a plain real grid (analytic mode).  gdev
 // (optional): device double multiplying both outputs after gscale.

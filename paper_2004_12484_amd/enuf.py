@@ -31,7 +31,7 @@ EXPORTS = (
     "enuf_set_option", "enuf_set_stream", "enuf_energy_forces", "enuf_energy_forces_noalloc",
     "enuf_energy_grad", "enuf_eval_token", "enuf_energy_grad_dev", "enuf_get_flags", "enuf_stage_copy",
     "enuf_stage_bytes", "enuf_get_timings", "enuf_get_step_timings", "enuf_status_string", "enuf_last_error",
-    "enuf_device_count", "enuf_select_params", "enuf_select_last_error",
+    "enuf_device_count", "enuf_select_params", "enuf_select_last_error", "enuf_copy_probe",
 )
 
 _lib = None
@@ -79,6 +79,7 @@ def load_library():
                                        ctypes.POINTER(d), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                        ctypes.POINTER(i32)]
     lib.enuf_select_last_error.restype = ctypes.c_char_p
+    lib.enuf_copy_probe.argtypes = [vp, vp, sz, vp]
     for name in EXPORTS:
         if name not in ("enuf_status_string", "enuf_last_error", "enuf_device_count", "enuf_select_last_error"):
             getattr(lib, name).restype = i32
@@ -350,3 +351,16 @@ def enuf_energy(x, q, engine):
 
 def device_count() -> int:
     return int(load_library().enuf_device_count())
+
+
+def copy_probe(src, dst, stream=None):
+    """Copy device tensor src into dst (same byte size, a multiple of 16)
+    with the library's plain copy kernel on `stream` (default: torch's
+    current stream): the achievable-bandwidth probe."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+    _check(load_library().enuf_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                          nbytes, ctypes.c_void_p(stream)))

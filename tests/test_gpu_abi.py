@@ -7,6 +7,7 @@
 * Graph replay (ENUF_OPT_GRAPH) gives the results of the launched sequence
   on every replay, with eager work and synchronisations between replays, and
   captures again when the arguments or options change.
+* The copy probe copies exactly and rejects bad arguments.
 """
 import ctypes
 
@@ -125,3 +126,22 @@ def test_graph_replay_matches_launched_sequence(mode):
     eng.set_option(enuf.OPT_TIMING, 4)
     with pytest.raises(enuf.EnufError):
         eng.timings()
+
+
+def test_copy_probe_copies_and_validates():
+    """enuf_copy_probe (the bandwidth probe): an exact copy of sizes that do
+    and do not fill the kernel's four-deep loop, and the argument checks."""
+    lib = enuf.load_library()
+    for nbytes in (16, 16 * 1000 + 16 * 7, 3 << 20):
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        enuf.copy_probe(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+    src = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    vp = ctypes.c_void_p
+    assert lib.enuf_copy_probe(vp(src.data_ptr()), vp(dst.data_ptr()), 20, None) == enuf.ENUF_EINVAL
+    assert lib.enuf_copy_probe(vp(src.data_ptr() + 4), vp(dst.data_ptr()), 16, None) == enuf.ENUF_EINVAL
+    assert lib.enuf_copy_probe(None, vp(dst.data_ptr()), 16, None) == enuf.ENUF_EINVAL
+    assert lib.enuf_copy_probe(vp(src.data_ptr()), vp(src.data_ptr() + 16), 32, None) == enuf.ENUF_EINVAL
