@@ -283,6 +283,39 @@ __device__ int block_exscan_int(int v, int *total) {
   return before + inc - v;
 }
 
+// Block order for kernels whose neighbouring blocks read overlapping data:
+// workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8),
+// each XCD with its own L2.  Mapping hardware block b to logical block
+// (b mod 8) n/8 + b/8 gives each XCD one contiguous eighth of the logical
+// order (a slab of the grid), so the overlap between neighbours is fetched
+// into one L2 instead of several.  A bijection when n is a multiple of 8;
+// other counts keep the plain order.
+__device__ __forceinline__ int xcd_slab(int b, int n) {
+  return (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+}
+
+// block-wide exclusive count of a flag: the wave's ballot and a masked bit
+// count give the rank inside the wave, one LDS word per wave the rest
+// (NW: the block's wave count when known at compile time, else 0)
+template <int NW = 0>
+__device__ int block_exscan_flag(bool f, int *total) {
+  __shared__ int wcnt[16];
+  const int wv = threadIdx.x >> 6, nw = NW > 0 ? NW : (int)(blockDim.x >> 6);
+  const unsigned long long m = __ballot(f);
+  const int inwave = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  if ((threadIdx.x & 63) == 0) wcnt[wv] = __popcll(m);
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int t = wcnt[k];
+    if (k < wv) before += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inwave;
+}
+
 // --------------------------------------------------------------------------
 // prep and sort: wrap, bin keys, two-level counting sort, charge sums
 //
@@ -1132,7 +1165,7 @@ __global__ __launch_bounds__(spread_block<R>()) void k_spread(const real4<R> *__
       // staging slots in candidate order (a block scan, so the order of the
       // sums is the same from run to run)
       int ns;
-      const int slot = block_exscan_int(hit ? 1 : 0, &ns);
+      const int slot = block_exscan_flag(hit, &ns);
       if (tid == 0) nstaged = ns;
       if (hit) {
         // loop over the shorter of z and x; lanes cover the other two axes
@@ -1267,8 +1300,9 @@ template <int P, bool F32MAC>
 __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ part, const int *__restrict__ off_t,
                                                      const int *__restrict__ runs, int nruns, Geom g,
                                                      const double *__restrict__ scal, float *__restrict__ grid) {
-  // rows 0..15: e^x, 16..23: e^y, 24..31: q e^z, one column per staged particle
-  __shared__ __align__(16) float E[32][kSpreadLd];
+  // rows 0..15: e^x, 16..23: e^y, 24..31: q e^z, one column per staged
+  // particle; row 32 takes the weights that fall outside the tile
+  __shared__ __align__(16) float E[33][kSpreadLd];
   __shared__ int rstart[kMaxRuns], rpre[kMaxRuns + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int t = blockIdx.x;
@@ -1289,6 +1323,10 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
   for (int nb = 0; nb < 4; ++nb) acc[nb] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
 
   for (int base = 0; base < total; base += kSpreadK) {
+    // clear rows 0..31 (every column the products read), 16 bytes per store;
+    // the scan's barriers below order these stores before the weights'
+    for (int e = tid; e < 32 * kSpreadLd / 4; e += blockDim.x)
+      reinterpret_cast<float4_t *>(&E[0][0])[e] = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
     const int c = base + tid;
     int start[3] = {0, 0, 0};
     float fr[3] = {0.0f, 0.0f, 0.0f}, qv = 0.0f;
@@ -1320,14 +1358,8 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
     // columns up to the next multiple of 16 (read by the last k-step) are
     // zeroed, so no stale LDS word ever enters a product
     int ns;
-    const int slot = block_exscan_int(hit ? 1 : 0, &ns);
-    {
-      const int npad = ((ns + 15) & ~15) - ns;
-      for (int e = tid; e < 32 * npad; e += blockDim.x) E[e / npad][ns + e % npad] = 0.0f;
-    }
+    const int slot = block_exscan_flag<4>(hit, &ns);
     if (hit) {
-#pragma unroll
-      for (int r = 0; r < 32; ++r) E[r][slot] = 0.0f;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         float w[P];
@@ -1336,7 +1368,8 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           const int idx = start[d] + j;
-          if (idx >= 0 && idx < g.T[d]) E[row0[d] + idx][slot] = w[j] * sc;
+          const int row = (unsigned)idx < (unsigned)g.T[d] ? row0[d] + idx : 32;
+          (&E[0][0])[__umul24((unsigned)row, (unsigned)kSpreadLd) + slot] = w[j] * sc;
         }
       }
     }
@@ -1344,11 +1377,8 @@ __global__ __launch_bounds__(256) void k_spread_mfma(const float4 *__restrict__ 
     const int nsteps = (ns + 15) >> 4;
     for (int ks = wv; ks < nsteps; ks += 4) {
       const int k0 = 16 * ks + 4 * (lane >> 4);
-      float4_t a = *reinterpret_cast<const float4_t *>(&E[lane & 15][k0]);
-      // columns past the staged count may hold stale (finite) weights
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (k0 + r >= ns) a[r] = 0.0f;
+      // columns ns .. 16 nsteps - 1 hold the zeros stored above
+      const float4_t a = *reinterpret_cast<const float4_t *>(&E[lane & 15][k0]);
       const float4_t by = *reinterpret_cast<const float4_t *>(&E[16 + (lane & 7)][k0]);
       if constexpr (F32MAC) {
         // FP32 products: four 16x16x4 FP32 MFMAs per column block, the j-th
@@ -2226,7 +2256,7 @@ __global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R>
   // block = SY x SZ spread tiles along y and z (fewer at the top of an axis
   // with an odd tile count)
   const int nsy = (g.nt[1] + SY - 1) / SY;
-  int t = blockIdx.x;
+  int t = xcd_slab(blockIdx.x, gridDim.x);
   const int tx = t % g.nt[0];
   t /= g.nt[0];
   const int ty0 = SY * (t % nsy);
@@ -2453,6 +2483,10 @@ __device__ __forceinline__ float erfc_with_exp(float x, float e) {
 __device__ __forceinline__ double erfc_with_exp(double x, double) { return erfc(x); }
 __device__ __forceinline__ float exp_fast(float v) { return __expf(v); }
 __device__ __forceinline__ double exp_fast(double v) { return exp(v); }
+// 2^v: the hardware base-2 exponential in single precision (arguments here
+// lie in [-13, 0], far from its denormal range)
+__device__ __forceinline__ float exp2_r(float v) { return __builtin_amdgcn_exp2f(v); }
+__device__ __forceinline__ double exp2_r(double v) { return exp2(v); }
 __device__ __forceinline__ float rsqrt_r(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_r(double v) { return 1.0 / sqrt(v); }
 
@@ -2497,7 +2531,8 @@ __device__ __forceinline__ void slater_factors(R t, R et, R &bu, R &bf) {
 // potential; self times q_i the self potential.
 template <typename R>
 struct PairConst {
-  R L[3], iL[3], rc2, al, al2, c2a;
+  R L[3], iL[3], rc2, al, c2a;
+  R nal2l2e;  // -alpha^2 log2(e): exp(-alpha^2 r^2) = 2^(nal2l2e r^2)
   R isl;  // 1 / lambda_e of Slater-smeared charges (ENUF-DPD); 0 for point charges
   double bg, self;
 };
@@ -2511,8 +2546,8 @@ static PairConst<R> pair_const(const Geom &g) {
   }
   c.rc2 = (R)(g.rc * g.rc);
   c.al = (R)g.alpha;
-  c.al2 = (R)(g.alpha * g.alpha);
   c.c2a = (R)(2.0 * g.alpha / sqpi);
+  c.nal2l2e = (R)(-g.alpha * g.alpha * 1.4426950408889634074);
   c.isl = g.slater > 0.0 ? (R)(1.0 / g.slater) : R(0);
   c.bg = -g.ke * pi / (g.L[0] * g.L[1] * g.L[2] * g.alpha * g.alpha);
   c.self = -2.0 * g.ke * g.alpha / sqpi;
@@ -2588,7 +2623,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
   const R L0 = pc.L[0], L1 = pc.L[1], L2 = pc.L[2];
   const R iL0 = pc.iL[0], iL1 = pc.iL[1], iL2 = pc.iL[2];
   const R rc2 = pc.rc2;
-  const R al = pc.al, al2 = pc.al2;
+  const R al = pc.al;
   const R c2a = pc.c2a;
   const double phi_bg = pc.bg * scal[0];
   const double c_self = pc.self;
@@ -2712,11 +2747,11 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(const real4<R> *__restrict_
             const int b = __builtin_ctzll(mask);
             mask &= mask - 1ull;
             R ddx, ddy, ddz;
-            const R qj = sep(b0 + Gh * b, ddx, ddy, ddz);
+            const R qj = sep(b0 + (int)__umul24((unsigned)Gh, (unsigned)b), ddx, ddy, ddz);
             const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             const R ir = r2 > R(0) ? rsqrt_r(r2) : R(0);  // r = 0 (itself) marked above, adds nothing
             const R r = r2 * ir;
-            const R ex = exp_fast(-al2 * r2);
+            const R ex = exp2_r(pc.nal2l2e * r2);
             R ec = erfc_with_exp(al * r, ex) * ir;
             R fs = qj * (ec + c2a * ex) * ir * ir;
             if (pc.isl > R(0)) {
