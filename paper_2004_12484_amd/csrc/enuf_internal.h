@@ -12,6 +12,7 @@ namespace enuf {
 constexpr int kBlock = 256;          // threads per block for per-particle kernels
 constexpr int kGatherBlock = 128;    // threads per block of the interpolation kernels
 constexpr int kGatherTileBlock = 256;  // threads per tile in the LDS-staged interpolation
+constexpr int kGatherTileBlockBig = 512;  // threads per 2 x 2-tile block of the same
 constexpr int kTileX = 16;           // spread tile (grid points) before clamping to M/2
 constexpr int kTileY = 8;
 constexpr int kTileZ = 8;

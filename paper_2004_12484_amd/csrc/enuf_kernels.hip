@@ -2244,7 +2244,7 @@ __device__ __forceinline__ double pick(int b, double x, double y) {
 }
 
 template <typename R, int P, bool GRAD, typename FT, int SY, int SZ, int KL>
-__global__ __launch_bounds__(kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
+__global__ __launch_bounds__(SY * SZ > 1 ? kGatherTileBlockBig : kGatherTileBlock) void k_gather_tile(const real4<R> *__restrict__ part,
                                                                   const int *__restrict__ perm,
                                                                   const int *__restrict__ off_t, Geom g,
                                                                   const FT *__restrict__ field, R pref,
@@ -3141,7 +3141,7 @@ static void launch_gather_as(const Geom &g, const Work &w, hipStream_t st, R pre
   const size_t lds2 = gather_tile_lds<FT, P>(g, 2, 2);
   if (sizeof(FT) == sizeof(R) && lds2 <= 65536) {
     const int nb = g.nt[0] * ((g.nt[1] + 1) / 2) * ((g.nt[2] + 1) / 2);
-    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2, kGatherLanesBig>), dim3(nb), dim3(kGatherTileBlock), lds2, st,
+    hipLaunchKernelGGL((k_gather_tile<R, P, GRAD, FT, 2, 2, kGatherLanesBig>), dim3(nb), dim3(kGatherTileBlockBig), lds2, st,
                        (const real4<R> *)w.part_t, w.perm_t, w.off_t, g, (const FT *)w.field, pref, gs, ss, vo,
                        so);
     return;
