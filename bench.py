@@ -116,7 +116,8 @@ def sources_sha():
 def measured_traffic(workload, phase):
     """HBM bytes per launch of the phase's kernel from rocprofv3 FETCH_SIZE and
     WRITE_SIZE counters (each scaled by what the counter reads for a plain
-    copy of known size), if they were taken on this exact build."""
+    copy of known size), if they were taken on this exact build.  workload is
+    the benchmark's workload key: the counters belong to its setting."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path) or phase not in PHASE_KERNEL:
         return None
@@ -497,20 +498,20 @@ def main():
     if dom in ab:
         achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, dom),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, dom),
                 "bytes_per_launch": ab[dom], "frac_of_copy": achieved / copy["gbs"]}
     else:
         pairs = pair_count(w, nq)
         peak = FP32_VALU_TFLOPS if rs == 4 else FP64_VALU_TFLOPS
         achieved = pairs * PAIR_FLOPS / (phases[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(w.name, dom),
+                "frac": achieved / peak, "traffic": measured_traffic(args.workload, dom),
                 "flops_per_launch": pairs * PAIR_FLOPS, "unordered_pairs": pairs}
     hbm = {k: ab[k] / (phases[k] * 1e-3) / 1e9 for k in ab}
     # the HBM-bound gates: spread and gather against the HBM peak, with the
     # counter bytes of their kernels beside them when measured on this build
     gates = {k: {"algorithmic_bytes": ab[k], "ms": phases[k], "gbs": hbm[k], "frac": hbm[k] / HBM_PEAK_GBS,
-                 "frac_of_copy": hbm[k] / copy["gbs"], "counter_bytes": measured_traffic(w.name, k)}
+                 "frac_of_copy": hbm[k] / copy["gbs"], "counter_bytes": measured_traffic(args.workload, k)}
              for k in ("spread", "gather")}
 
     rec = {
