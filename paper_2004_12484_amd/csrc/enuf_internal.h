@@ -31,6 +31,8 @@ constexpr int kSortChunkMax = 2048;  // particles grouped in LDS at a time by th
 constexpr int kSortStageBlock = 1024;  // threads per block of the staging pass
 constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass
 constexpr int kSortFineRegs = 8;     // particles per thread held in registers by the fine pass
+constexpr int kFineOutBytes = 32768; // LDS window through which the fine pass writes its records
+constexpr int kFineWindowBuckets = 512;  // at most this many buckets (2 blocks on each of 256 CUs) use it
 constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)
 constexpr int kESlots = 64;    // energy partials per part outside the deterministic mode (block mod 64)
 constexpr int kDetSmall = 32;  // deterministic bin order: bins up to this size sorted by one thread
@@ -90,6 +92,7 @@ struct SortPlan {
   int sh[2];
   int nb[2];
   int nbins[2];  // keys per order: kTileBins*ntiles, 2*ncells
+  int window;    // fine pass: write through the LDS window (else gather reads)
 };
 SortPlan sort_plan(const Geom &g, int real_bytes);
 size_t sort_stage_lds(const SortPlan &sp, int real_bytes);

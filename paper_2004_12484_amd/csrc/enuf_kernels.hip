@@ -835,19 +835,24 @@ __global__ __launch_bounds__(kSortStageBlock) void k_sort_stage(const R *__restr
 // Pass 3: one workgroup per bucket (tile buckets, then cell buckets): counting
 // sort of the bucket's particles by fine key in LDS, bin offsets of the
 // bucket's keys, particles and source indices in final order.  A bucket of at
-// most kSortFineRegs*blockDim particles keeps keys and ranks in registers and
-// builds the inverse permutation in LDS, so the final order is written
-// contiguously (reads gathered from the staged bucket instead); a larger one
-// goes through global ranks and scattered writes.
-template <typename R>
-__global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const int *__restrict__ bbase,
-                                                              const real4<R> *__restrict__ stg_t,
-                                                              const int2 *__restrict__ ik_t, int *srank_t,
-                                                              const real4<R> *__restrict__ stg_c,
-                                                              const int2 *__restrict__ ik_c, int *srank_c,
-                                                              real4<R> *part_t, int *perm_t, int *off_t,
-                                                              real4<R> *part_c, int *perm_c, int *off_c,
-                                                              const int *need) {
+// most kSortFineRegs*blockDim particles keeps keys and ranks in registers,
+// then (WIN) also its records and source indices, read once and
+// coalesced, and writes them out through an LDS window of kFineOutBytes: each
+// pass places the records whose final slot falls in the window, then the
+// window goes to memory contiguously, so the permutation happens in LDS.
+// Otherwise it builds the inverse permutation in LDS and writes the final
+// order contiguously while the reads gather from the staged bucket (64 cache
+// lines per wave instruction: slow when every bucket's block is resident at
+// once and that latency is all there is, hidden behind the other blocks when
+// there are several rounds of them).  A larger bucket goes through global
+// ranks and scattered writes.
+template <typename R, bool WIN>
+__device__ __forceinline__ void sort_fine(const SortPlan &sp, const int *__restrict__ bbase,
+                                          const real4<R> *__restrict__ stg_t, const int2 *__restrict__ ik_t,
+                                          int *srank_t, const real4<R> *__restrict__ stg_c,
+                                          const int2 *__restrict__ ik_c, int *srank_c, real4<R> *part_t,
+                                          int *perm_t, int *off_t, real4<R> *part_c, int *perm_c, int *off_c,
+                                          const int *need) {
   if (need && *need == 0) return;
   constexpr int U = kSortFineRegs;
   extern __shared__ int lds_fine[];
@@ -865,19 +870,38 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
   int *perm = tiles ? perm_t : perm_c;
   int *off = tiles ? off_t : off_c;
   const int nt = blockDim.x, tid = threadIdx.x;
-  int *bin = lds_fine;                                   // [2^max sh] counts, then starts
-  int *inv = lds_fine + (1 << max(sp.sh[0], sp.sh[1]));  // [U*nt] bucket position -> staged index
+  int *bin = lds_fine;  // [2^max sh] counts, then starts
+  // after the bins either the output window (WN records, then their source
+  // indices) or the inverse permutation ([U*nt] bucket position -> staged index)
+  constexpr int WN = kFineOutBytes / (int)sizeof(real4<R>);
+  real4<R> *wrec = reinterpret_cast<real4<R> *>(lds_fine + (1 << max(sp.sh[0], sp.sh[1])));
+  int *wsrc = reinterpret_cast<int *>(wrec + WN);
+  int *inv = lds_fine + (1 << max(sp.sh[0], sp.sh[1]));
   const bool small = e - s <= U * nt;
 
   for (int f = tid; f < nf; f += nt) bin[f] = 0;
   __syncthreads();
-  int kk[U], rr[U];
+  int kk[U], rr[U], src[U];
+  int kr[U];  // window form: key << 16 | rank (key < 2^12, rank < 2^13), or -1
+  pod_t<real4<R>> rec[U];
   if (small) {
-    // every lane loads U keys (past the end: the bucket's last one again),
-    // so the loads go out together instead of one per branch
+    // every lane loads U (key, source index, record) triples (past the end:
+    // the bucket's last one again), so the loads go out together instead of
+    // one per branch
     int raw[U];
+    if (WIN) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) raw[u] = e > s ? ik[min(s + u * nt + tid, e - 1)].y : 0;
+      for (int u = 0; u < U; ++u) {
+        const int jc = e > s ? min(s + u * nt + tid, e - 1) : 0;
+        const int2 v = ik[jc];
+        raw[u] = v.y;
+        src[u] = v.x;
+        rec[u] = *reinterpret_cast<const pod_t<real4<R>> *>(stg + jc);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) raw[u] = e > s ? ik[min(s + u * nt + tid, e - 1)].y : 0;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = s + u * nt + tid;
@@ -885,6 +909,10 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) rr[u] = (unsigned)kk[u] < (unsigned)nf ? atomicAdd(&bin[kk[u]], 1) : 0;
+    if (WIN) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) kr[u] = (unsigned)kk[u] < (unsigned)nf ? (kk[u] << 16) | rr[u] : -1;
+    }
   } else {
     for (int j0 = s + tid; j0 < e; j0 += U * nt) {
 #pragma unroll
@@ -914,7 +942,7 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
     run += v;
   }
   __syncthreads();
-  if (small) {
+  if (small && !WIN) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if ((unsigned)kk[u] < (unsigned)nf) inv[bin[kk[u]] + rr[u]] = u * nt + tid;
@@ -943,6 +971,26 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
           perm[s + t0 + u * nt] = pv[u];
         }
     }
+  } else if (small) {
+    int pos[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pos[u] = kr[u] >= 0 ? bin[kr[u] >> 16] + (kr[u] & 0xFFFF) : -1;
+    for (int w0 = 0; w0 < e - s; w0 += WN) {
+      const int wn = min(WN, e - s - w0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if ((unsigned)(pos[u] - w0) < (unsigned)wn) {
+          *reinterpret_cast<pod_t<real4<R>> *>(wrec + pos[u] - w0) = rec[u];
+          wsrc[pos[u] - w0] = src[u];
+        }
+      __syncthreads();
+      for (int t = tid; t < wn; t += nt) {
+        *reinterpret_cast<pod_t<real4<R>> *>(part + s + w0 + t) =
+            *reinterpret_cast<const pod_t<real4<R>> *>(wrec + t);
+        perm[s + w0 + t] = wsrc[t];
+      }
+      __syncthreads();
+    }
   } else {
     for (int j0 = s + tid; j0 < e; j0 += U * nt) {
 #pragma unroll
@@ -958,6 +1006,30 @@ __global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const
       }
     }
   }
+}
+
+// The two forms as kernels: the gather form keeps few registers (two blocks
+// per CU with room to spare), the window form (FP32 only) is held to 64
+// registers (eight waves per SIMD: two 1024-thread blocks per CU).
+template <typename R>
+__global__ __launch_bounds__(kSortFineBlock) void k_sort_fine(SortPlan sp, const int *__restrict__ bbase,
+                                                              const real4<R> *__restrict__ stg_t,
+                                                              const int2 *__restrict__ ik_t, int *srank_t,
+                                                              const real4<R> *__restrict__ stg_c,
+                                                              const int2 *__restrict__ ik_c, int *srank_c,
+                                                              real4<R> *part_t, int *perm_t, int *off_t,
+                                                              real4<R> *part_c, int *perm_c, int *off_c,
+                                                              const int *need) {
+  sort_fine<R, false>(sp, bbase, stg_t, ik_t, srank_t, stg_c, ik_c, srank_c, part_t, perm_t, off_t, part_c, perm_c,
+                      off_c, need);
+}
+template <typename R>
+__global__ __launch_bounds__(kSortFineBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_sort_fine_win(
+    SortPlan sp, const int *__restrict__ bbase, const real4<R> *__restrict__ stg_t, const int2 *__restrict__ ik_t,
+    int *srank_t, const real4<R> *__restrict__ stg_c, const int2 *__restrict__ ik_c, int *srank_c,
+    real4<R> *part_t, int *perm_t, int *off_t, real4<R> *part_c, int *perm_c, int *off_c, const int *need) {
+  sort_fine<R, true>(sp, bbase, stg_t, ik_t, srank_t, stg_c, ik_c, srank_c, part_t, perm_t, off_t, part_c, perm_c,
+                     off_c, need);
 }
 
 // --------------------------------------------------------------------------
@@ -2858,7 +2930,11 @@ size_t sort_stage_lds(const SortPlan &sp, int real_bytes) {
 }
 
 size_t sort_fine_lds(const SortPlan &sp) {
-  return ((size_t)(1 << std::max(sp.sh[0], sp.sh[1])) + (size_t)kSortFineRegs * kSortFineBlock) * sizeof(int);
+  // bins, then the output window's records and source indices (at most
+  // kFineOutBytes / 16 of them) or the inverse permutation
+  const size_t win = kFineOutBytes + kFineOutBytes / 16 * sizeof(int);
+  const size_t inv = (size_t)kSortFineRegs * kSortFineBlock * sizeof(int);
+  return (size_t)(1 << std::max(sp.sh[0], sp.sh[1])) * sizeof(int) + std::max(win, inv);
 }
 
 SortPlan sort_plan(const Geom &g, int real_bytes) {
@@ -2877,6 +2953,9 @@ SortPlan sort_plan(const Geom &g, int real_bytes) {
     sp.sh[o] = sh;
     sp.nb[o] = (sp.nbins[o] + (1 << sh) - 1) >> sh;
   }
+  // the fine pass writes through its LDS window when every bucket's block
+  // can be resident at once (two 1024-thread blocks per CU)
+  sp.window = sp.nb[0] + sp.nb[1] <= kFineWindowBuckets;
   // largest staging chunk (a multiple of the block) that fits 64 KB of LDS;
   // zero (ungrouped staging) if none does
   for (sp.chunk = kSortChunkMax; sp.chunk >= kSortBlock; sp.chunk /= 2)
@@ -3240,10 +3319,20 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
   hipLaunchKernelGGL((k_sort_stage<R>), dim3(sp.nblk), dim3(kSortStageBlock), sort_stage_lds(sp, (int)sizeof(R)), st,
                      x, q, g, sp, (const int *)w.key_t, (const int *)w.key_c, (const int *)w.hist,
                      (const int *)w.bbase, (real4<R> *)w.stg_t, w.ik_t, (real4<R> *)w.stg_c, w.ik_c, need);
-  hipLaunchKernelGGL((k_sort_fine<R>), dim3(nbk), dim3(kSortFineBlock), lds_fine, st, sp, (const int *)w.bbase,
-                     (const real4<R> *)w.stg_t, (const int2 *)w.ik_t, w.key_t, (const real4<R> *)w.stg_c,
-                     (const int2 *)w.ik_c, w.key_c, (real4<R> *)w.part_t, w.perm_t, w.off_t,
-                     (real4<R> *)w.part_c, w.perm_c, w.off_c, need);
+  bool win = false;
+  if constexpr (sizeof(R) == 4) {  // the FP64 records do not fit the window form's registers
+    win = sp.window != 0;
+    if (win)
+      hipLaunchKernelGGL((k_sort_fine_win<R>), dim3(nbk), dim3(kSortFineBlock), lds_fine, st, sp,
+                         (const int *)w.bbase, (const real4<R> *)w.stg_t, (const int2 *)w.ik_t, w.key_t,
+                         (const real4<R> *)w.stg_c, (const int2 *)w.ik_c, w.key_c, (real4<R> *)w.part_t,
+                         w.perm_t, w.off_t, (real4<R> *)w.part_c, w.perm_c, w.off_c, need);
+  }
+  if (!win)
+    hipLaunchKernelGGL((k_sort_fine<R>), dim3(nbk), dim3(kSortFineBlock), lds_fine, st, sp, (const int *)w.bbase,
+                       (const real4<R> *)w.stg_t, (const int2 *)w.ik_t, w.key_t, (const real4<R> *)w.stg_c,
+                       (const int2 *)w.ik_c, w.key_c, (real4<R> *)w.part_t, w.perm_t, w.off_t,
+                       (real4<R> *)w.part_c, w.perm_c, w.off_c, need);
   if (g.det) {
     // bins in caller-index order; the key arrays (dead after the sort) hold
     // the lists of large bins, the staging arrays the moved records
