@@ -33,6 +33,7 @@ constexpr int kSortFineBlock = 1024; // threads per bucket in the fine pass
 constexpr int kSortFineRegs = 8;     // particles per thread held in registers by the fine pass
 constexpr int kFineOutBytes = 32768; // LDS window through which the fine pass writes its records
 constexpr int kFineWindowBuckets = 512;  // at most this many buckets (2 blocks on each of 256 CUs) use it
+constexpr int kFineWindowMin = 1024;     // ... or any number of buckets this full on average
 constexpr int kTabSlots = 11;  // FFT / influence table offsets (see table_size)
 constexpr int kESlots = 64;    // energy partials per part outside the deterministic mode (block mod 64)
 constexpr int kDetSmall = 32;  // deterministic bin order: bins up to this size sorted by one thread

@@ -843,9 +843,9 @@ __global__ __launch_bounds__(kSortStageBlock) void k_sort_stage(const R *__restr
 // Otherwise it builds the inverse permutation in LDS and writes the final
 // order contiguously while the reads gather from the staged bucket (64 cache
 // lines per wave instruction: slow when every bucket's block is resident at
-// once and that latency is all there is, hidden behind the other blocks when
-// there are several rounds of them).  A larger bucket goes through global
-// ranks and scattered writes.
+// once and that latency is all there is, or when the buckets are full; for
+// many sparse buckets the lighter first read wins).  A larger bucket goes
+// through global ranks and scattered writes.
 template <typename R, bool WIN>
 __device__ __forceinline__ void sort_fine(const SortPlan &sp, const int *__restrict__ bbase,
                                           const real4<R> *__restrict__ stg_t, const int2 *__restrict__ ik_t,
@@ -2954,7 +2954,8 @@ SortPlan sort_plan(const Geom &g, int real_bytes) {
     sp.nb[o] = (sp.nbins[o] + (1 << sh) - 1) >> sh;
   }
   // the fine pass writes through its LDS window when every bucket's block
-  // can be resident at once (two 1024-thread blocks per CU)
+  // can be resident at once (two 1024-thread blocks per CU); the evaluation
+  // also chooses it for well-filled buckets when it knows their fill
   sp.window = sp.nb[0] + sp.nb[1] <= kFineWindowBuckets;
   // largest staging chunk (a multiple of the block) that fits 64 KB of LDS;
   // zero (ungrouped staging) if none does
@@ -3288,7 +3289,10 @@ hipError_t launch_forward(const Geom &g, const Work &w, hipStream_t st, const R 
 
   mark(0);
   // prep: keys and per-block bucket counts
-  const SortPlan sp = sort_plan(g, (int)sizeof(R));
+  SortPlan sp = sort_plan(g, (int)sizeof(R));
+  // with every particle active (potentials requested) the buckets' fill is
+  // known here: well-filled buckets take the window form in any number
+  if (all_active && (long long)g.n >= (long long)kFineWindowMin * (sp.nb[0] + sp.nb[1])) sp.window = 1;
   const int nbk = sp.nb[0] + sp.nb[1];
   const size_t lds_cnt = (size_t)nbk * sizeof(int);
   const size_t lds_fine = sort_fine_lds(sp);
