@@ -1787,6 +1787,43 @@ __device__ __forceinline__ void fft_stage_ip(int ln, int lns, int lnb, const Cx<
   }
 }
 
+// The same stage with post(v, ob) applied to the butterfly's outputs (in
+// registers, before they are written back): output r goes to element
+// ob + (r << lns).
+template <typename R, int RAD, int DIR, typename Post>
+__device__ __forceinline__ void fft_stage_ip_post(int ln, int lns, int lnb, const Cx<R> *__restrict__ tw, Cx<R> *X,
+                                                  Post post) {
+  constexpr int LR = RAD == 16 ? 4 : (RAD == 8 ? 3 : 2);
+  const int lq = ln - LR;
+  const int lt = ln - lns - LR;
+  const int w = threadIdx.x;
+  const bool act = w < (1 << (lq + lnb));
+  const int f = w & ((1 << lnb) - 1);
+  const int j = (w >> lnb) & ((1 << lq) - 1);
+  const int k = j & ((1 << lns) - 1);
+  const int ob = ((j - k) << LR) + k;
+  Cx<R> v[RAD];
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = X[((j + (r << lq)) << lnb) + f];
+    if (lns > 0) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        Cx<R> wr = tw[(r * k) << lt];
+        if (DIR > 0) wr = cconj(wr);
+        v[r] = cmul(v[r], wr);
+      }
+    }
+    dft<R, RAD, DIR>(v);
+    post(v, ob);
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) X[((ob + (r << lns)) << lnb) + f] = v[r];
+  }
+}
+
 // z pass for a single field from the potential spectrum (analytic forces),
 // lengths 128 and 256 (two stages): one LDS buffer of n x 16 pencils holds
 // the spectrum throughout (stages in place), so a block reads and writes
@@ -1956,9 +1993,9 @@ __global__ __launch_bounds__(kBlock) void k_z_psi(const Cx<R> *__restrict__ spec
     }
   }
   __syncthreads();
-  if (L1 == 4) fft_stage_ip<R, 16, -1>(lnz, 4, lnb, tw_z, X);
-  else fft_stage_ip<R, 8, -1>(lnz, 4, lnb, tw_z, X);
-  __syncthreads();
+  // second forward stage; its outputs (element kz = ob + 16 r of pencil f,
+  // in natural order) take the influence factor and give their energy
+  // before they are written back
   double en = 0.0;
   {
     const int f = threadIdx.x & (nb - 1);
@@ -1967,14 +2004,19 @@ __global__ __launch_bounds__(kBlock) void k_z_psi(const Cx<R> *__restrict__ spec
     const R kxy2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky];
     const R sxy = sx[kx] * sy[ky];
     const R wk = kx > 0 ? R(2) : R(1);
-    for (int kz = threadIdx.x >> lnb; kz < n; kz += blockDim.x >> lnb) {
-      const int e = (kz << lnb) + f;
-      const R k2 = kxy2 + kvz[kz] * kvz[kz];
-      const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
-      const Cx<R> r = X[e];
-      en += (double)(wk * gv * (r.x * r.x + r.y * r.y));
-      X[e] = Cx<R>{gv * r.x, gv * r.y};
-    }
+    auto scale = [&](auto &v, int ob) {
+      constexpr int RAD = sizeof(v) / sizeof(v[0]);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        const int kz = ob + (r << 4);
+        const R k2 = kxy2 + kvz[kz] * kvz[kz];
+        const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
+        en += (double)(wk * gv * (v[r].x * v[r].x + v[r].y * v[r].y));
+        v[r] = Cx<R>{gv * v[r].x, gv * v[r].y};
+      }
+    };
+    if (L1 == 4) fft_stage_ip_post<R, 16, -1>(lnz, 4, lnb, tw_z, X, scale);
+    else fft_stage_ip_post<R, 8, -1>(lnz, 4, lnb, tw_z, X, scale);
   }
   __syncthreads();
   // inverse: first stage in place, the second writes global memory
