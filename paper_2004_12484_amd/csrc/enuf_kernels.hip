@@ -2015,13 +2015,33 @@ __global__ __launch_bounds__(kBlock) void k_z_psi(const Cx<R> *__restrict__ spec
         v[r] = Cx<R>{gv * v[r].x, gv * v[r].y};
       }
     };
-    if (L1 == 4) fft_stage_ip_post<R, 16, -1>(lnz, 4, lnb, tw_z, X, scale);
-    else fft_stage_ip_post<R, 8, -1>(lnz, 4, lnb, tw_z, X, scale);
+    if (L1 == 4) {
+      // n = 256: the second forward stage leaves a thread elements j + 16 r,
+      // exactly the inputs of the first inverse (radix-16, span-1) stage's
+      // butterfly j, so both run on the same registers: read, twiddle,
+      // forward DFT, influence, inverse DFT, then write elements 16 j + r
+      const int w = threadIdx.x;
+      const int f = w & (nb - 1), j = (w >> lnb) & 15;
+      Cx<R> v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = X[((j + (r << 4)) << lnb) + f];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw_z[r * j]);
+      dft<R, 16, -1>(v);
+      scale(v, j);
+      dft<R, 16, 1>(v);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) X[(((j << 4) + r) << lnb) + f] = v[r];
+    } else {
+      fft_stage_ip_post<R, 8, -1>(lnz, 4, lnb, tw_z, X, scale);
+      __syncthreads();
+      // inverse: first stage in place
+      fft_stage_ip<R, 16, 1>(lnz, 0, lnb, tw_z, X);
+    }
   }
   __syncthreads();
-  // inverse: first stage in place, the second writes global memory
-  fft_stage_ip<R, 16, 1>(lnz, 0, lnb, tw_z, X);
-  __syncthreads();
+  // inverse: the second stage writes global memory
   {
     const int LR = L1;
     const int lq = lnz - LR;
