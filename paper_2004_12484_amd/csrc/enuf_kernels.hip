@@ -1910,8 +1910,10 @@ __global__ __launch_bounds__(512) void k_z_psi512(const Cx<R> *__restrict__ spec
   __syncthreads();
   fft_stage_ip_n<R, 16, -1, 1>(lnz, 4, lnb, tw_z, X);
   __syncthreads();
-  fft_stage_ip_n<R, 2, -1, 8>(lnz, 8, lnb, tw_z, X);
-  __syncthreads();
+  // last forward stage (radix 2, span 256), influence and energy, first
+  // inverse stage (radix 2, span 1) on the same registers: forward
+  // butterfly jb leaves elements jb and jb + 256 in natural order, which
+  // are the inverse butterfly jb's inputs; it writes elements 2 jb, 2 jb + 1
   double en = 0.0;
   {
     const int pidx = (int)p0 + f;
@@ -1919,19 +1921,39 @@ __global__ __launch_bounds__(512) void k_z_psi512(const Cx<R> *__restrict__ spec
     const R kxy2 = kvx[kx] * kvx[kx] + kvy[ky] * kvy[ky];
     const R sxy = sx[kx] * sy[ky];
     const R wk = kx > 0 ? R(2) : R(1);
-    for (int kz = tid >> lnb; kz < n; kz += blockDim.x >> lnb) {
-      const int e = (kz << lnb) + f;
-      const R k2 = kxy2 + kvz[kz] * kvz[kz];
-      const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
-      const Cx<R> r = X[e];
-      en += (double)(wk * gv * (r.x * r.x + r.y * r.y));
-      X[e] = Cx<R>{gv * r.x, gv * r.y};
+    Cx<R> a[8], b[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int jb = (tid >> lnb) + 32 * t;  // butterfly 0..255 of pencil f
+      a[t] = X[(jb << lnb) + f];
+      b[t] = cmul(X[((jb + 256) << lnb) + f], tw_z[jb]);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int jb = (tid >> lnb) + 32 * t;
+      Cx<R> u0 = cadd(a[t], b[t]), u1 = csub(a[t], b[t]);  // kz = jb, jb + 256
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        Cx<R> &u = r == 0 ? u0 : u1;
+        const int kz = jb + 256 * r;
+        const R k2 = kxy2 + kvz[kz] * kvz[kz];
+        const R gv = k2 > R(0) ? sxy * sz[kz] * recip_r(k2) : R(0);
+        en += (double)(wk * gv * (u.x * u.x + u.y * u.y));
+        u = Cx<R>{gv * u.x, gv * u.y};
+      }
+      a[t] = cadd(u0, u1);
+      b[t] = csub(u0, u1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int jb = (tid >> lnb) + 32 * t;
+      X[((2 * jb) << lnb) + f] = a[t];
+      X[((2 * jb + 1) << lnb) + f] = b[t];
     }
   }
   __syncthreads();
-  // inverse: radix 2 (span 1) and radix 16 (span 2) in place
-  fft_stage_ip_n<R, 2, 1, 8>(lnz, 0, lnb, tw_z, X);
-  __syncthreads();
+  // inverse: radix 16 (span 2) in place
   fft_stage_ip_n<R, 16, 1, 1>(lnz, 1, lnb, tw_z, X);
   __syncthreads();
   // last stage: radix 16, span 32, to global memory
